@@ -1,0 +1,161 @@
+/*
+ * sale.h -- C ABI of libsale.so: the SALE (Simplified Arbitrary
+ * Lagrangian-Eulerian) hydrodynamics step on one MI355X (gfx950).
+ *
+ * One step is the Lagrangian phase on a logically structured 3D hex mesh
+ * followed by the Eulerian rezone and advection (a face-flux remap) back to
+ * the fixed mesh -- the "Lagrangian rezoning", "Eulerian rezoning" and
+ * "Advection" kernels of the ScalSALE framework (arXiv 2209.01983, Sec. I-D
+ * and Table I), for a single ideal gas, p = (gamma-1) rho e (Sec. I-C/I-D),
+ * with cell-centred density and internal energy and vertex velocities
+ * (cell and vertex quantities, Sec. III-B/III-C). The paper prints no scheme
+ * equations; the library computes the scheme fixed by the project's FP64
+ * oracle: acoustic half-step pressure predictor, von Neumann-Richtmyer +
+ * Landshoff viscosity, compatible energy, exact trilinear swept volumes,
+ * first-order unsplit donor-cell remap, dual-mesh momentum remap with a
+ * kinetic-energy fix, reflective walls on all six faces.
+ *
+ * The caller-supplied buffers follow the paper's zero-copy "pointer to the
+ * data" hand-off (Point_to_data, Sec. III-A) and its C interoperability
+ * (Sec. I-D, Table I; Sec. II-A).
+ *
+ * Conventions for every function:
+ *  - Return int: SALE_OK (0) on success, < 0 on error, > 0 informational.
+ *    Nothing throws, aborts or exits.
+ *  - Ownership: the caller owns every device buffer (workspace, arena,
+ *    field destinations). The library owns only small host structs, freed by
+ *    sale_destroy / sale_pool_destroy. It never calls hipMalloc/hipFree and
+ *    never synchronises the device; only functions documented as
+ *    synchronising wait on the caller's stream.
+ *  - Streams: a `hip_stream` argument is a hipStream_t (NULL = the null
+ *    stream). All device work of a context is ordered on its stream.
+ *  - Threading: a context is single-threaded; different contexts may be used
+ *    from different threads on different streams.
+ *  - Layout of fields exchanged with the caller ("logical layout"):
+ *      cell (i,j,k), 0<=i<nx  -> index i + nx*(j + ny*k)
+ *      node (i,j,k), 0<=i<=nx -> index i + (nx+1)*(j + (ny+1)*k)
+ *    Velocity is three node arrays (u, v, w), i.e. structure of arrays.
+ */
+#ifndef SALE_H
+#define SALE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- return codes ------------------------------------------------------ */
+#define SALE_OK 0
+#define SALE_DONE 1       /* t >= t_end: the run is complete             */
+#define SALE_EINVAL (-1)  /* invalid argument, config or initial data   */
+#define SALE_ENOMEM (-2)  /* workspace / arena too small                 */
+#define SALE_EHIP (-3)    /* a HIP runtime call failed; see sale_strerror */
+#define SALE_ENUMERIC (-4) /* non-finite / non-positive density, negative
+                              or non-finite energy, non-finite dt          */
+#define SALE_ETANGLE (-5) /* a predictor or Lagrangian cell volume <= 0   */
+#define SALE_EBUSY (-6)   /* pool admission refused (no slot or budget)   */
+
+/* ---- enums ------------------------------------------------------------- */
+#define SALE_FP64 0       /* every quantity in FP64                      */
+#define SALE_MIXED32 1    /* FP32 storage and bulk arithmetic; FP64 for
+                             node displacements, swept volumes, volume
+                             differences, the CFL dt and the totals       */
+#define SALE_BC_REFLECT 0 /* reflective (slip) wall                      */
+
+#define SALE_SOD_X 0          /* Sod tube along x                        */
+#define SALE_SEDOV_CORNER 1   /* Sedov blast deposited in cell (0,0,0)   */
+#define SALE_USER 2           /* caller arrays                           */
+
+/* status flag bits (sticky, see sale_status) */
+#define SALE_FLAG_TANGLE 1u   /* V* <= 0 or V^L <= 0                      */
+#define SALE_FLAG_NUMERIC 2u  /* rho <= 0, e < 0, non-finite value or dt  */
+
+/* field mask bits for sale_fields (destinations in ascending bit order) */
+#define SALE_F_RHO (1u << 0)    /* cells: density                         */
+#define SALE_F_E (1u << 1)      /* cells: specific internal energy        */
+#define SALE_F_P (1u << 2)      /* cells: pressure (gamma-1) rho e        */
+#define SALE_F_Q (1u << 3)      /* cells: artificial viscosity of the state */
+#define SALE_F_U (1u << 4)      /* nodes: x velocity                      */
+#define SALE_F_V (1u << 5)      /* nodes: y velocity                      */
+#define SALE_F_W (1u << 6)      /* nodes: z velocity                      */
+#define SALE_F_STATE (1u << 7)  /* host double[4]: t, steps, next dt, status */
+#define SALE_F_TOTALS (1u << 8) /* host double[2]: total mass, total energy */
+
+/* ---- configuration ----------------------------------------------------- */
+typedef struct {
+  int32_t nx, ny, nz;       /* cells per axis, >= 1                         */
+  double lo[3], hi[3];      /* box; cell size (hi-lo)/n per axis, hi > lo   */
+  double gamma;             /* ideal-gas ratio of specific heats, > 1       */
+  double cfl;               /* Courant number, 0 < cfl < 1 (default 0.5)    */
+  double c_quad, c_lin;     /* viscosity coefficients >= 0 (1.0, 0.5)       */
+  double t_end;             /* end time >= 0                                */
+  int32_t precision;        /* SALE_FP64 | SALE_MIXED32                     */
+  int32_t bc[6];            /* per face (-x,+x,-y,+y,-z,+z): SALE_BC_REFLECT */
+} sale_config;
+
+typedef struct {
+  int32_t kind;             /* SALE_SOD_X | SALE_SEDOV_CORNER | SALE_USER   */
+  double sod[5];            /* x_split, rho_L, p_L, rho_R, p_R (u = 0); a cell
+                               is "left" iff its centre x < x_split          */
+  double sedov[3];          /* rho0, p0, E_dep: uniform rho0, e = p0/((gamma-1)
+                               rho0); cell (0,0,0) gets e = E_dep/(rho0 V0)  */
+  const double *rho, *e;    /* SALE_USER: cells, logical layout             */
+  const double *u, *v, *w;  /* SALE_USER: nodes, logical layout; wall-normal
+                               components are set to zero on the walls      */
+  int32_t user_on_device;   /* SALE_USER arrays are device (1) or host (0)  */
+  double t0;                /* initial time (restart), <= t_end             */
+  int64_t step0;            /* initial step count (restart)                 */
+} sale_problem;
+
+typedef struct sale_ctx sale_ctx;
+
+/* Bytes of device workspace one run of `cfg` needs (256-byte aligned
+ * sub-buffers). The caller allocates it (e.g. a torch uint8 tensor) and keeps
+ * it alive until sale_destroy. SALE_EINVAL for an invalid config. */
+int sale_workspace_bytes(const sale_config *cfg, size_t *bytes);
+
+/* Validate cfg and the problem, lay out the workspace d_ws (device,
+ * ws_bytes >= sale_workspace_bytes), write the initial state and its first
+ * time step on `hip_stream` (asynchronous), and return a new context.
+ * SALE_USER arrays must be finite with rho > 0 and e >= 0 (SALE_EINVAL
+ * otherwise; device arrays are checked on the device and reported by the
+ * first sale_status/sale_run). Host user arrays are copied before return. */
+int sale_init(const sale_config *cfg, const sale_problem *prob, void *d_ws, size_t ws_bytes,
+              void *hip_stream, sale_ctx **out);
+
+/* Enqueue one Lagrange + remap step (asynchronous). A step enqueued after the
+ * run reached t_end, or after an error flag was raised, changes nothing. */
+int sale_step(sale_ctx *ctx);
+
+/* Run until t >= t_end or until max_steps more steps were taken. t_end < 0
+ * keeps the configured end time; otherwise it replaces it (the last step is
+ * clipped to land on it). Synchronises the stream every few steps to read the
+ * device status. Returns SALE_DONE when t_end was reached, SALE_OK when
+ * max_steps ran out first, SALE_ETANGLE / SALE_ENUMERIC on a flagged step. */
+int sale_run(sale_ctx *ctx, double t_end, int64_t max_steps);
+
+/* Copy the fields selected by `mask` into dst[0..], one pointer per set bit in
+ * ascending bit order. Field arrays are written in the logical layout as
+ * double (as_fp64 != 0) or in the storage type (double for SALE_FP64, float
+ * for SALE_MIXED32), to device (dst_on_device != 0) or host memory. STATE and
+ * TOTALS always go to host double arrays. Synchronises the stream. */
+int sale_fields(sale_ctx *ctx, uint32_t mask, void *const *dst, int dst_on_device, int as_fp64);
+
+/* Synchronise the stream and return the sticky status flags (SALE_FLAG_*).
+ * Returns SALE_ETANGLE / SALE_ENUMERIC if a flag is set, else SALE_DONE if
+ * t >= t_end, else SALE_OK. */
+int sale_status(sale_ctx *ctx, int32_t *status_flags);
+
+/* Free the context's host memory (the workspace stays the caller's). */
+void sale_destroy(sale_ctx *ctx);
+
+/* Static description of a return code (SALE_EHIP: the last HIP error of the
+ * calling thread). */
+const char *sale_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SALE_H */

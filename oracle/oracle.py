@@ -57,6 +57,8 @@ def lib():
         L.orc_init_sedov.argtypes = [cfg] + [C.c_double] * 3 + [P] * 5
         L.orc_geometry.restype = C.c_int
         L.orc_geometry.argtypes = [cfg, C.c_void_p, P, P, P, P]
+        L.orc_derived.restype = C.c_int
+        L.orc_derived.argtypes = [cfg, C.c_void_p, P, P, P, P, P, P, P]
         L.orc_face_swept_volume.restype = C.c_double
         L.orc_face_swept_volume.argtypes = [P, C.c_double, C.c_double]
         _lib = L
@@ -205,6 +207,17 @@ class Oracle:
         arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (dX, dY, dZ)]
         rc = lib().orc_geometry(C.byref(self._cfg), self._ws, *(_ptr(a) for a in arrs), _ptr(VL))
         return rc, VL
+
+    def derived(self, s: State):
+        """(p, q) of a state."""
+        self._check(s)
+        p = np.zeros(self.g.cell_shape)
+        q = np.zeros(self.g.cell_shape)
+        rc = lib().orc_derived(C.byref(self._cfg), self._ws, _ptr(s.rho), _ptr(s.e), _ptr(s.u), _ptr(s.v),
+                               _ptr(s.w), _ptr(p), _ptr(q))
+        if rc != OK:
+            raise ValueError(f"orc_derived: {rc}")
+        return p, q
 
     def totals(self, s: State):
         """(total mass, total energy) of a state."""

@@ -32,7 +32,9 @@
  * results do not depend on the thread count. Reductions (max, sums) are
  * serial.
  */
+#define _GNU_SOURCE
 #include <math.h>
+#include <sys/mman.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -123,6 +125,19 @@ static double corner_sum(const orc_config *g, double dx, double dy, double dz, i
 /* ------------------------------------------------------------------ */
 void orc_ws_destroy(orc_ws *w);
 
+/* malloc + zero-fill in parallel (first touch spread over the threads, so
+ * that the page faults of a multi-GB workspace do not serialise). */
+static double *zalloc(size_t n) {
+  void *v = NULL;
+  size_t bytes = n * sizeof(double) + 64;
+  if (posix_memalign(&v, (size_t)1 << 21, bytes) != 0) return NULL;
+  madvise(v, bytes, MADV_HUGEPAGE); /* fewer page faults on GB-sized arrays */
+  double *p = (double *)v;
+#pragma omp parallel for schedule(static)
+  for (size_t a = 0; a < n; a++) p[a] = 0.0;
+  return p;
+}
+
 orc_ws *orc_ws_create(const orc_config *g) {
   if (!g || g->nx < 1 || g->ny < 1 || g->nz < 1) return NULL;
   orc_ws *w = (orc_ws *)calloc(1, sizeof(orc_ws));
@@ -138,18 +153,18 @@ orc_ws *orc_ws_create(const orc_config *g) {
                       &w->P2, &w->P3, &w->K, &w->mn, &w->dK, &w->un, &w->vn, &w->wn};
   int ok = 1;
   for (size_t a = 0; a < sizeof(cells) / sizeof(cells[0]); a++)
-    ok &= (*cells[a] = (double *)calloc(nc, sizeof(double))) != NULL;
+    ok &= (*cells[a] = zalloc(nc)) != NULL;
   for (size_t a = 0; a < sizeof(nodes) / sizeof(nodes[0]); a++)
-    ok &= (*nodes[a] = (double *)calloc(nn, sizeof(double))) != NULL;
-  ok &= (w->dvx = (double *)calloc(nfx, sizeof(double))) != NULL;
-  ok &= (w->mux = (double *)calloc(nfx, sizeof(double))) != NULL;
-  ok &= (w->ex = (double *)calloc(nfx, sizeof(double))) != NULL;
-  ok &= (w->dvy = (double *)calloc(nfy, sizeof(double))) != NULL;
-  ok &= (w->muy = (double *)calloc(nfy, sizeof(double))) != NULL;
-  ok &= (w->ey = (double *)calloc(nfy, sizeof(double))) != NULL;
-  ok &= (w->dvz = (double *)calloc(nfz, sizeof(double))) != NULL;
-  ok &= (w->muz = (double *)calloc(nfz, sizeof(double))) != NULL;
-  ok &= (w->ez = (double *)calloc(nfz, sizeof(double))) != NULL;
+    ok &= (*nodes[a] = zalloc(nn)) != NULL;
+  ok &= (w->dvx = zalloc(nfx)) != NULL;
+  ok &= (w->mux = zalloc(nfx)) != NULL;
+  ok &= (w->ex = zalloc(nfx)) != NULL;
+  ok &= (w->dvy = zalloc(nfy)) != NULL;
+  ok &= (w->muy = zalloc(nfy)) != NULL;
+  ok &= (w->ey = zalloc(nfy)) != NULL;
+  ok &= (w->dvz = zalloc(nfz)) != NULL;
+  ok &= (w->muz = zalloc(nfz)) != NULL;
+  ok &= (w->ez = zalloc(nfz)) != NULL;
   if (!ok) { orc_ws_destroy(w); return NULL; }
   return w;
 }
@@ -739,11 +754,13 @@ int orc_init_sedov(const orc_config *g, double rho0, double p0, double edep, dou
   spacing(g, &dx, &dy, &dz);
   const double V0 = dx * dy * dz;
   size_t nc = (size_t)NX * NY * NZ, nn = (size_t)(NX + 1) * (NY + 1) * (NZ + 1);
+#pragma omp parallel for schedule(static)
   for (size_t c = 0; c < nc; c++) {
     rho[c] = rho0;
     e[c] = p0 / ((g->gamma - 1.0) * rho0);
   }
   e[0] = edep / (rho0 * V0);
+#pragma omp parallel for schedule(static)
   for (size_t n = 0; n < nn; n++) u[n] = v[n] = w[n] = 0.0;
   return ORC_OK;
 }
@@ -781,4 +798,16 @@ int orc_geometry(const orc_config *g, orc_ws *W, const double *dX, const double 
   int rc = stage_geometry(g, 1.0, W);
   for (size_t c = 0; c < nc; c++) VL[c] = W->VL[c];
   return rc;
+}
+
+/* Pressure p = (gamma-1) rho e and artificial viscosity q of a state (O2, O4),
+ * for checking exported derived fields. */
+int orc_derived(const orc_config *g, orc_ws *W, const double *rho, const double *e,
+                const double *u, const double *v, const double *w, double *p, double *q) {
+  if (!config_valid(g) || !W || W->nx != g->nx || W->ny != g->ny || W->nz != g->nz)
+    return ORC_EINVAL;
+  stage_cells_eos_div_q(g, rho, e, u, v, w, W);
+  size_t nc = (size_t)NX * NY * NZ;
+  for (size_t c = 0; c < nc; c++) { p[c] = W->p[c]; q[c] = W->q[c]; }
+  return ORC_OK;
 }
