@@ -44,12 +44,12 @@ def algorithmic_bytes(n):
     return 2 * (2 * ncell + 3 * nnode) * 8  # read + write rho, e, u, v, w (FP64)
 
 
-def gpu_bench(n, steps, warmup):
+def gpu_bench(n, steps, warmup, precision=0):
     import torch
 
     from paper_2209_01983_amd import sale
 
-    cfg = sale.make_config(n, n, n, hi=(1.2, 1.2, 1.2), t_end=1.0)
+    cfg = sale.make_config(n, n, n, hi=(1.2, 1.2, 1.2), t_end=1.0, precision=precision)
     run = sale.SaleRun(cfg, sale.sedov_problem())
     run.step(warmup)
     torch.cuda.synchronize()
@@ -96,7 +96,8 @@ def main():
               "(multi-GPU halo exchange is a design note, not built); use --gpus 1", file=sys.stderr)
         sys.exit(2)
     n = a.n
-    ms, wall, t_sim = gpu_bench(n, a.steps, a.warmup)
+    ms, wall, t_sim = gpu_bench(n, a.steps, a.warmup, precision=0)
+    ms32, _, _ = gpu_bench(n, a.steps, a.warmup, precision=1)
     cells = n ** 3
     value = cells * 1e3 / ms
     abytes = algorithmic_bytes(n)
@@ -116,6 +117,8 @@ def main():
         "data": "synthetic (Sedov blast initial state generated on the device)",
         "config": {"workload": f"sedov {n}^3 octant, FP64 Lagrange + donor-cell remap", "cells": cells,
                    "precision": "fp64", "sim_time_end_of_window": t_sim},
+        "mixed32": {"value": cells * 1e3 / ms32, "unit": "cell-updates/s", "ms_per_step": ms32,
+                    "precision": "FP32 bulk, FP64 geometry/dt/totals"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "kernel": "whole step (all step kernels), algorithmic bytes "

@@ -137,10 +137,11 @@ int sale_step(sale_ctx *ctx);
 int sale_run(sale_ctx *ctx, double t_end, int64_t max_steps);
 
 /* Copy the fields selected by `mask` into dst[0..], one pointer per set bit in
- * ascending bit order. Field arrays are written in the logical layout as
- * double (as_fp64 != 0) or in the storage type (double for SALE_FP64, float
- * for SALE_MIXED32), to device (dst_on_device != 0) or host memory. STATE and
- * TOTALS always go to host double arrays. Synchronises the stream. */
+ * ascending bit order, to device (dst_on_device != 0) or host memory, in the
+ * logical layout. RHO, E, U, V, W are written as double (as_fp64 != 0) or in
+ * the storage type (double for SALE_FP64, float for SALE_MIXED32); P and Q
+ * are always double. STATE and TOTALS always go to host double arrays.
+ * Synchronises the stream. */
 int sale_fields(sale_ctx *ctx, uint32_t mask, void *const *dst, int dst_on_device, int as_fp64);
 
 /* Synchronise the stream and return the sticky status flags (SALE_FLAG_*).

@@ -1,6 +1,6 @@
 // sale_api.cpp -- host side of the libsale C ABI declared in include/sale.h:
 // argument validation, workspace layout, enqueueing of the step kernels on
-// the caller's stream, status polling and field export.
+// the caller's stream, status polling and field export, for both precisions.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdio.h>
@@ -8,14 +8,13 @@
 
 #include <algorithm>
 #include <new>
-#include <vector>
 
 #include "../../include/sale.h"
 #include "sale_impl.h"
 
 using sale::Ctl;
-using sale::Fields64;
 using sale::Mesh;
+using sale::Work;
 
 struct sale_ctx {
   sale_config cfg;
@@ -24,11 +23,14 @@ struct sale_ctx {
   void *ws;
   size_t ws_bytes;
   Ctl *ctl;
-  Fields64 f;
+  int precision;
+  Work<double> w64;
+  Work<float> w32;
+  int cur;  // which of the two state buffers holds the current state
   double t_end;
 };
 
-namespace {
+namespace sale_host {
 
 thread_local char g_hip_msg[256] = "no HIP error recorded";
 
@@ -36,12 +38,6 @@ int hip_fail(hipError_t e, const char *what) {
   snprintf(g_hip_msg, sizeof(g_hip_msg), "%s: %s", what, hipGetErrorString(e));
   return SALE_EHIP;
 }
-
-#define HIP_TRY(expr)                               \
-  do {                                              \
-    hipError_t e_ = (expr);                         \
-    if (e_ != hipSuccess) return hip_fail(e_, #expr); \
-  } while (0)
 
 bool finite_pos(double x) { return isfinite(x) && x > 0.0; }
 
@@ -57,7 +53,7 @@ int validate_config(const sale_config *c) {
   if (!isfinite(c->c_quad) || !(c->c_quad >= 0.0) || !isfinite(c->c_lin) || !(c->c_lin >= 0.0))
     return SALE_EINVAL;
   if (!isfinite(c->t_end) || !(c->t_end >= 0.0)) return SALE_EINVAL;
-  if (c->precision != SALE_FP64) return SALE_EINVAL;  // MIXED32 not in this build
+  if (c->precision != SALE_FP64 && c->precision != SALE_MIXED32) return SALE_EINVAL;
   for (int a = 0; a < 6; a++)
     if (c->bc[a] != SALE_BC_REFLECT) return SALE_EINVAL;
   const int64_t ncell = (int64_t)c->nx * c->ny * c->nz;
@@ -88,6 +84,10 @@ Mesh make_mesh(const sale_config *c) {
   return m;
 }
 
+size_t ws_bytes_for(const Mesh &m, int precision) {
+  return precision == SALE_FP64 ? sale::workspace_bytes<double>(m) : sale::workspace_bytes<float>(m);
+}
+
 int validate_problem(const sale_problem *p, const Mesh &m) {
   if (!p) return SALE_EINVAL;
   if (!isfinite(p->t0) || p->step0 < 0) return SALE_EINVAL;
@@ -116,10 +116,25 @@ int validate_problem(const sale_problem *p, const Mesh &m) {
   }
 }
 
-int read_ctl(sale_ctx *x, Ctl *out) {
-  HIP_TRY(hipMemcpyAsync(out, x->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, x->stream));
-  HIP_TRY(hipStreamSynchronize(x->stream));
-  return SALE_OK;
+template <typename R>
+hipError_t init_problem(const Mesh &m, Ctl *ctl, const Work<R> &w, const sale_problem *p, double t_end,
+                        hipStream_t s) {
+  switch (p->kind) {
+    case SALE_SOD_X:
+      return sale::launch_init_sod<R>(m, ctl, w, p->sod, p->t0, p->step0, t_end, s);
+    case SALE_SEDOV_CORNER:
+      return sale::launch_init_sedov<R>(m, ctl, w, p->sedov, p->t0, p->step0, t_end, s);
+    default: {
+      const double *const src[5] = {p->rho, p->e, p->u, p->v, p->w};
+      return sale::launch_init_user<R>(m, ctl, w, src, p->user_on_device != 0, p->t0, p->step0, t_end, s);
+    }
+  }
+}
+
+int read_ctl(hipStream_t s, const Ctl *d, Ctl *out) {
+  hipError_t e = hipMemcpyAsync(out, d, sizeof(Ctl), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  return e == hipSuccess ? SALE_OK : hip_fail(e, "read control block");
 }
 
 int status_code(const Ctl &c) {
@@ -128,7 +143,33 @@ int status_code(const Ctl &c) {
   return c.t >= c.t_end ? SALE_DONE : SALE_OK;
 }
 
-}  // namespace
+double next_dt(const Ctl &c, const Mesh &m) {
+  double amax = 0.0;
+  memcpy(&amax, &c.amax_bits, sizeof(amax));
+  const double rem = c.t_end - c.t;
+  double dt = amax > 0.0 ? m.cfl * m.h / amax : rem;
+  return dt > rem ? rem : dt;
+}
+
+// Enqueue one step from state buffer `cur` into the other one. A no-op step
+// (after t_end or an error) copies the state across, so the current state is
+// always in buffer `cur` as the host counts it.
+hipError_t enqueue_step(sale_ctx *x) {
+  hipError_t e = x->precision == SALE_FP64 ? sale::launch_step<double>(x->m, x->ctl, x->w64, x->cur, x->stream)
+                                           : sale::launch_step<float>(x->m, x->ctl, x->w32, x->cur, x->stream);
+  if (e == hipSuccess) x->cur ^= 1;
+  return e;
+}
+
+}  // namespace sale_host
+
+using namespace sale_host;
+
+#define HIP_TRY(expr)                                 \
+  do {                                                \
+    hipError_t e_ = (expr);                           \
+    if (e_ != hipSuccess) return hip_fail(e_, #expr); \
+  } while (0)
 
 extern "C" {
 
@@ -136,8 +177,7 @@ int sale_workspace_bytes(const sale_config *cfg, size_t *bytes) {
   if (!bytes) return SALE_EINVAL;
   int rc = validate_config(cfg);
   if (rc != SALE_OK) return rc;
-  Mesh m = make_mesh(cfg);
-  *bytes = sale::workspace_bytes_fp64(m, nullptr);
+  *bytes = ws_bytes_for(make_mesh(cfg), cfg->precision);
   return SALE_OK;
 }
 
@@ -150,7 +190,7 @@ int sale_init(const sale_config *cfg, const sale_problem *prob, void *d_ws, size
   Mesh m = make_mesh(cfg);
   if ((rc = validate_problem(prob, m)) != SALE_OK) return rc;
   if (!d_ws || ((uintptr_t)d_ws & 255u)) return SALE_EINVAL;
-  if (ws_bytes < sale::workspace_bytes_fp64(m, nullptr)) return SALE_ENOMEM;
+  if (ws_bytes < ws_bytes_for(m, cfg->precision)) return SALE_ENOMEM;
   sale_ctx *x = new (std::nothrow) sale_ctx;
   if (!x) return SALE_ENOMEM;
   x->cfg = *cfg;
@@ -159,30 +199,15 @@ int sale_init(const sale_config *cfg, const sale_problem *prob, void *d_ws, size
   x->ws = d_ws;
   x->ws_bytes = ws_bytes;
   x->t_end = cfg->t_end;
-  sale::layout_fp64(m, d_ws, &x->ctl, &x->f);
-  hipError_t e = hipSuccess;
-  const double t0 = prob->t0;
-  switch (prob->kind) {
-    case SALE_SOD_X:
-      e = sale::launch_init_sod(m, x->ctl, x->f, prob->sod, t0, prob->step0, x->t_end, x->stream);
-      break;
-    case SALE_SEDOV_CORNER:
-      e = sale::launch_init_sedov(m, x->ctl, x->f, prob->sedov, t0, prob->step0, x->t_end, x->stream);
-      break;
-    default: {
-      const hipMemcpyKind kind = prob->user_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
-      const size_t cb = (size_t)m.ncell * sizeof(double), nb = (size_t)m.nnode * sizeof(double);
-      if ((e = hipMemcpyAsync(x->f.rho, prob->rho, cb, kind, x->stream)) == hipSuccess &&
-          (e = hipMemcpyAsync(x->f.e, prob->e, cb, kind, x->stream)) == hipSuccess &&
-          (e = hipMemcpyAsync(x->f.u, prob->u, nb, kind, x->stream)) == hipSuccess &&
-          (e = hipMemcpyAsync(x->f.v, prob->v, nb, kind, x->stream)) == hipSuccess &&
-          (e = hipMemcpyAsync(x->f.w, prob->w, nb, kind, x->stream)) == hipSuccess) {
-        // host sources must not be touched after return: wait for the copies
-        if (!prob->user_on_device) e = hipStreamSynchronize(x->stream);
-        if (e == hipSuccess)
-          e = sale::launch_init_user(m, x->ctl, x->f, t0, prob->step0, x->t_end, x->stream);
-      }
-    }
+  x->precision = cfg->precision;
+  x->cur = 0;
+  hipError_t e;
+  if (x->precision == SALE_FP64) {
+    sale::layout<double>(m, d_ws, &x->ctl, &x->w64);
+    e = init_problem<double>(m, x->ctl, x->w64, prob, x->t_end, x->stream);
+  } else {
+    sale::layout<float>(m, d_ws, &x->ctl, &x->w32);
+    e = init_problem<float>(m, x->ctl, x->w32, prob, x->t_end, x->stream);
   }
   if (e != hipSuccess) {
     delete x;
@@ -194,7 +219,7 @@ int sale_init(const sale_config *cfg, const sale_problem *prob, void *d_ws, size
 
 int sale_step(sale_ctx *x) {
   if (!x) return SALE_EINVAL;
-  HIP_TRY(sale::launch_step_fp64(x->m, x->ctl, x->f, x->stream));
+  HIP_TRY(enqueue_step(x));
   return SALE_OK;
 }
 
@@ -206,7 +231,7 @@ int sale_run(sale_ctx *x, double t_end, int64_t max_steps) {
     HIP_TRY(sale::launch_set_t_end(x->ctl, t_end, x->stream));
   }
   Ctl c;
-  int rc = read_ctl(x, &c);
+  int rc = read_ctl(x->stream, x->ctl, &c);
   if (rc != SALE_OK) return rc;
   if ((rc = status_code(c)) != SALE_OK) return rc;
   int64_t left = max_steps;
@@ -215,12 +240,9 @@ int sale_run(sale_ctx *x, double t_end, int64_t max_steps) {
   int64_t chunk = 4;
   while (left > 0) {
     const int64_t n = std::min(left, chunk);
-    for (int64_t s = 0; s < n; s++) {
-      hipError_t e = sale::launch_step_fp64(x->m, x->ctl, x->f, x->stream);
-      if (e != hipSuccess) return hip_fail(e, "sale_run");
-    }
+    for (int64_t s = 0; s < n; s++) HIP_TRY(enqueue_step(x));
     left -= n;
-    if ((rc = read_ctl(x, &c)) != SALE_OK) return rc;
+    if ((rc = read_ctl(x->stream, x->ctl, &c)) != SALE_OK) return rc;
     if ((rc = status_code(c)) != SALE_OK) return rc;
     // size the next chunk from the observed step rate, so that few enqueued
     // steps land past t_end (those are no-ops)
@@ -239,7 +261,7 @@ int sale_run(sale_ctx *x, double t_end, int64_t max_steps) {
 int sale_status(sale_ctx *x, int32_t *flags) {
   if (!x) return SALE_EINVAL;
   Ctl c;
-  int rc = read_ctl(x, &c);
+  int rc = read_ctl(x->stream, x->ctl, &c);
   if (rc != SALE_OK) return rc;
   if (flags) *flags = (int32_t)c.status;
   return status_code(c);
@@ -248,53 +270,67 @@ int sale_status(sale_ctx *x, int32_t *flags) {
 int sale_fields(sale_ctx *x, uint32_t mask, void *const *dst, int dst_on_device, int as_fp64) {
   if (!x || (mask && !dst)) return SALE_EINVAL;
   if (mask & ~((SALE_F_TOTALS << 1) - 1u)) return SALE_EINVAL;
-  (void)as_fp64;  // storage is FP64 in this build
   const Mesh &m = x->m;
   const hipMemcpyKind kind = dst_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
-  const size_t cb = (size_t)m.ncell * sizeof(double), nb = (size_t)m.nnode * sizeof(double);
+  const bool fp64 = x->precision == SALE_FP64;
+  double *scratch = fp64 ? x->w64.scratch : x->w32.scratch;
   int slot = 0;
   for (uint32_t bit = 1; bit <= SALE_F_TOTALS; bit <<= 1) {
     if (!(mask & bit)) continue;
     void *d = dst[slot++];
     if (!d) return SALE_EINVAL;
+    int which = -1;
     switch (bit) {
-      case SALE_F_RHO: HIP_TRY(hipMemcpyAsync(d, x->f.rho, cb, kind, x->stream)); break;
-      case SALE_F_E: HIP_TRY(hipMemcpyAsync(d, x->f.e, cb, kind, x->stream)); break;
-      case SALE_F_P:
-      case SALE_F_Q:
-        HIP_TRY(sale::launch_derived_fp64(m, x->f, bit == SALE_F_P ? 0 : 1, x->f.scratch, x->stream));
-        HIP_TRY(hipMemcpyAsync(d, x->f.scratch, cb, kind, x->stream));
-        // the scratch array is reused by the next derived field: wait
-        HIP_TRY(hipStreamSynchronize(x->stream));
-        break;
-      case SALE_F_U: HIP_TRY(hipMemcpyAsync(d, x->f.u, nb, kind, x->stream)); break;
-      case SALE_F_V: HIP_TRY(hipMemcpyAsync(d, x->f.v, nb, kind, x->stream)); break;
-      case SALE_F_W: HIP_TRY(hipMemcpyAsync(d, x->f.w, nb, kind, x->stream)); break;
-      case SALE_F_STATE: {
-        Ctl c;
-        int rc = read_ctl(x, &c);
-        if (rc != SALE_OK) return rc;
-        double *o = (double *)d;
-        double amax = 0.0;
-        memcpy(&amax, &c.amax_bits, sizeof(amax));
-        const double rem = c.t_end - c.t;
-        double dtn = amax > 0.0 ? m.cfl * m.h / amax : rem;
-        if (dtn > rem) dtn = rem;
-        o[0] = c.t;
-        o[1] = (double)c.step;
-        o[2] = dtn;
-        o[3] = (double)c.status;
-        break;
+      case SALE_F_RHO: which = 0; break;
+      case SALE_F_E: which = 1; break;
+      case SALE_F_P: which = 2; break;
+      case SALE_F_Q: which = 3; break;
+      case SALE_F_U: which = 4; break;
+      case SALE_F_V: which = 5; break;
+      case SALE_F_W: which = 6; break;
+      default: break;
+    }
+    if (which >= 0) {
+      const int64_t n = which >= 4 ? m.nnode : m.ncell;
+      const bool derived = which == 2 || which == 3;
+      if (!derived && (fp64 || !as_fp64)) {  // a stored array, copied as is
+        const void *src;
+        size_t esz;
+        if (fp64) {
+          const sale::State<double> &s = x->w64.s[x->cur];
+          const double *arr[7] = {s.rho, s.e, nullptr, nullptr, s.u, s.v, s.w};
+          src = arr[which];
+          esz = sizeof(double);
+        } else {
+          const sale::State<float> &s = x->w32.s[x->cur];
+          const float *arr[7] = {s.rho, s.e, nullptr, nullptr, s.u, s.v, s.w};
+          src = arr[which];
+          esz = sizeof(float);
+        }
+        HIP_TRY(hipMemcpyAsync(d, src, (size_t)n * esz, kind, x->stream));
+      } else {  // widened or derived: through the scratch array (always double)
+        HIP_TRY(fp64 ? sale::launch_export<double>(m, x->w64, x->cur, which, scratch, x->stream)
+                     : sale::launch_export<float>(m, x->w32, x->cur, which, scratch, x->stream));
+        HIP_TRY(hipMemcpyAsync(d, scratch, (size_t)n * sizeof(double), kind, x->stream));
+        HIP_TRY(hipStreamSynchronize(x->stream));  // the scratch array is reused next
       }
-      case SALE_F_TOTALS: {
-        HIP_TRY(sale::launch_totals_fp64(m, x->ctl, x->f, x->stream));
-        Ctl c;
-        int rc = read_ctl(x, &c);
-        if (rc != SALE_OK) return rc;
-        ((double *)d)[0] = c.totals[0];
-        ((double *)d)[1] = c.totals[1];
-        break;
-      }
+    } else if (bit == SALE_F_STATE) {
+      Ctl c;
+      int rc = read_ctl(x->stream, x->ctl, &c);
+      if (rc != SALE_OK) return rc;
+      double *o = (double *)d;
+      o[0] = c.t;
+      o[1] = (double)c.step;
+      o[2] = next_dt(c, m);
+      o[3] = (double)c.status;
+    } else if (bit == SALE_F_TOTALS) {
+      HIP_TRY(fp64 ? sale::launch_totals<double>(m, x->ctl, x->w64, x->cur, x->stream)
+                   : sale::launch_totals<float>(m, x->ctl, x->w32, x->cur, x->stream));
+      Ctl c;
+      int rc = read_ctl(x->stream, x->ctl, &c);
+      if (rc != SALE_OK) return rc;
+      ((double *)d)[0] = c.totals[0];
+      ((double *)d)[1] = c.totals[1];
     }
   }
   HIP_TRY(hipStreamSynchronize(x->stream));

@@ -1,5 +1,5 @@
 // sale_impl.h -- internal declarations of libsale (device control block,
-// workspace layout, kernel launchers). Not part of the public ABI.
+// workspace layout, run descriptors, kernel launchers). Not part of the ABI.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -20,10 +20,10 @@ struct Mesh {
   int64_t ncell, nnode;
 };
 
-// Device control block (one per run), at the start of the workspace.
-// `done` is decided once per step by the step's first kernel and read by
-// every later kernel of the step, so a step after t_end or after an error
-// flag changes nothing.
+// Device control block (one per run). `done` is decided once per step by the
+// step's first kernel and read by every later kernel of the step, so a step
+// after t_end or after an error flag changes nothing. The two counters are
+// used by the persistent multi-run kernel only.
 struct Ctl {
   double t;           // time of the state after the step in flight
   double dt;          // dt of the step in flight
@@ -34,47 +34,98 @@ struct Ctl {
   unsigned int status;  // sticky SALE_FLAG_* bits
   unsigned int done;    // this step is a no-op
   double totals[2];   // mass, energy (written by the diagnostics kernels)
-  double pad[6];
+  unsigned int tiles_done;  // persistent kernel: finished tiles of the current phase
+  unsigned int phase;       // persistent kernel: phase counter of the run
+  long long step_target;    // persistent kernel: stop after this many steps
+  double pad[3];
 };
 
-// FP64 workspace: state plus the temporaries of the multi-pass step.
-// Face arrays are stored per cell: the face at the cell's lower side along
-// that axis (zero on the domain's lower boundary); a cell's upper face is its
-// +axis neighbour's lower face, or a wall (zero) on the last layer.
-struct Fields64 {
-  double *rho, *e;          // state, cells
-  double *u, *v, *w;        // state, nodes
-  double *ps;               // P*: predicted pressure + q
-  double *rhoL, *eL;        // Lagrangian density and energy
-  double *dvx, *dvy, *dvz;  // swept volumes of the lower faces
-  double *mux, *muy, *muz;  // donor mass fluxes of the lower faces
-  double *ex, *ey, *ez;     // donor energy fluxes of the lower faces
-  double *M, *rn, *epre;    // remapped mass, density, energy before the KE fix
-  double *u1, *v1, *w1;     // Lagrangian end velocity u'
-  double *dkm;              // kinetic-energy defect per unit new nodal mass
-  double *scratch;          // one spare cell array (derived fields)
-  double *partial;          // reduction partials (diagnostics)
-  int64_t npartial;
+// One copy of the state, logical layout (see include/sale.h). R is the
+// storage type of the bulk quantities: double (SALE_FP64) or float
+// (SALE_MIXED32).
+template <typename R>
+struct State {
+  R *rho, *e;    // cells
+  R *u, *v, *w;  // nodes
 };
 
-size_t workspace_bytes_fp64(const Mesh &m, size_t *ctl_off);
-void layout_fp64(const Mesh &m, void *ws, Ctl **ctl, Fields64 *f);
+// Per-cell results of the Lagrangian phase handed from the first step kernel
+// to the second: rho^L, e^L and the swept volumes of the cell's three lower
+// faces (x face at its lower x side, etc.; zero on the domain boundary). A
+// cell's upper face is its +axis neighbour's lower face, or a wall. Swept
+// volumes are FP64 in both precisions.
+template <typename R>
+struct Geo {
+  R *rl, *el;
+  double *dvx, *dvy, *dvz;
+};
 
-// Initial states (asynchronous on `s`).
-hipError_t launch_init_sod(const Mesh &m, Ctl *ctl, const Fields64 &f, const double sod[5],
-                           double t0, long long step0, double t_end, hipStream_t s);
-hipError_t launch_init_sedov(const Mesh &m, Ctl *ctl, const Fields64 &f, const double sedov[3],
-                             double t0, long long step0, double t_end, hipStream_t s);
-// User arrays already copied into the state: zero wall-normal velocities,
-// reset the control block and compute the first signal speed.
-hipError_t launch_init_user(const Mesh &m, Ctl *ctl, const Fields64 &f, double t0,
-                            long long step0, double t_end, hipStream_t s);
+// Workspace of one run: two states (ping-pong), the Lagrangian end velocity
+// u' and the Lagrangian cell results, reduction partials, and one scratch
+// array of max(cells, nodes) doubles (conversions, derived fields).
+template <typename R>
+struct Work {
+  State<R> s[2];
+  R *up, *vp, *wp;
+  Geo<R> geo;
+  double *partial;
+  double *scratch;
+};
+
+// Launch decomposition of a z-marching step kernel: tiles of 32 x CH columns,
+// the z extent split into segments so that the grid fills the chip.
+struct Grid2 {
+  int tx, ty, nseg, seglen;  // tiles per axis, z segments, planes per segment
+  __host__ __device__ int blocks() const { return tx * ty * nseg; }
+};
+
+// Everything a step kernel needs about one run, for one step from state
+// buffer `cur` into `nxt`.
+template <typename R>
+struct RunArgs {
+  Mesh m;
+  Ctl *ctl;
+  State<R> cur, nxt;
+  R *up, *vp, *wp;
+  Geo<R> geo;
+  Grid2 ga, gb;  // decompositions of the Lagrange and remap kernels
+};
+
+Grid2 grid_lagrange(const Mesh &m, int target_blocks);
+Grid2 grid_remap(const Mesh &m, int target_blocks);
+constexpr int kStepThreads = 512;  // block size of both z-marching kernels
+
+template <typename R>
+size_t workspace_bytes(const Mesh &m);
+template <typename R>
+void layout(const Mesh &m, void *ws, Ctl **ctl, Work<R> *w);
+
+// Initial states into w.s[0] (asynchronous on `s`).
+template <typename R>
+hipError_t launch_init_sod(const Mesh &m, Ctl *ctl, const Work<R> &w, const double sod[5], double t0,
+                           long long step0, double t_end, hipStream_t s);
+template <typename R>
+hipError_t launch_init_sedov(const Mesh &m, Ctl *ctl, const Work<R> &w, const double sedov[3], double t0,
+                             long long step0, double t_end, hipStream_t s);
+// User arrays (double): copied through the scratch array into w.s[0], wall-
+// normal velocities zeroed, control block reset, first signal speed computed.
+template <typename R>
+hipError_t launch_init_user(const Mesh &m, Ctl *ctl, const Work<R> &w, const double *const src[5],
+                            bool on_device, double t0, long long step0, double t_end, hipStream_t s);
 
 hipError_t launch_set_t_end(Ctl *ctl, double t_end, hipStream_t s);
-hipError_t launch_step_fp64(const Mesh &m, Ctl *ctl, const Fields64 &f, hipStream_t s);
-hipError_t launch_totals_fp64(const Mesh &m, Ctl *ctl, const Fields64 &f, hipStream_t s);
-// p (which = 0) or q (which = 1) of the current state into `out` (cells).
-hipError_t launch_derived_fp64(const Mesh &m, const Fields64 &f, int which, double *out,
-                               hipStream_t s);
+// One step from w.s[cur] into w.s[1 - cur].
+template <typename R>
+hipError_t launch_step(const Mesh &m, Ctl *ctl, const Work<R> &w, int cur, hipStream_t s);
+template <typename R>
+hipError_t launch_totals(const Mesh &m, Ctl *ctl, const Work<R> &w, int cur, hipStream_t s);
+// Step arguments of one run (state w.s[cur] -> w.s[1 - cur]); the kernels'
+// z segmentation aims at `target_blocks` blocks per kernel.
+template <typename R>
+RunArgs<R> run_args(const Mesh &m, Ctl *ctl, const Work<R> &w, int cur, int target_blocks);
+// Field `which` of state w.s[cur] as doubles into `out`: 0 rho, 1 e, 2 p, 3 q
+// (cells), 4 u, 5 v, 6 w (nodes).
+template <typename R>
+hipError_t launch_export(const Mesh &m, const Work<R> &w, int cur, int which, double *out, hipStream_t s);
 
 }  // namespace sale

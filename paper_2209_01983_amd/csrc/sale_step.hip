@@ -1,0 +1,465 @@
+// sale_step.hip -- single-run kernels of libsale for gfx950: the step
+// (k_begin, k_lagrange, k_remap around the tile functions of sale_tiles.h),
+// initial states, diagnostics, field export and the workspace layout, for
+// both precisions (R = double: SALE_FP64, R = float: SALE_MIXED32).
+#include "sale_tiles.h"
+
+namespace sale {
+namespace {
+
+// Tile shapes (columns per tile = 32 x CH) and the register cap (minimum
+// waves per SIMD) of the two z-marching kernels; tuned on MI355X.
+constexpr int CH = 16;
+#ifndef SALE_WAVES_STEP
+#define SALE_WAVES_STEP 4
+#endif
+static_assert(32 * CH == kStepThreads, "step kernels use 512-thread blocks");
+constexpr int TPB = 256;  // simple per-element kernels
+
+// ---------------------------------------------------------------------------------
+// k_begin: the step's time step (O3) and the done decision
+// ---------------------------------------------------------------------------------
+__global__ void k_begin(Mesh m, Ctl *ctl) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  if (ctl->status != 0u || ctl->t >= ctl->t_end) {
+    ctl->done = 1u;
+    return;
+  }
+  const double amax = __longlong_as_double((long long)ctl->amax_bits);
+  const double rem = ctl->t_end - ctl->t;
+  double dt = amax > 0.0 ? m.cfl * m.h / amax : rem;
+  if (dt > rem) dt = rem;
+  if (!(dt > 0.0) || !isfinite(dt)) {
+    ctl->status |= SALE_FLAG_NUMERIC;
+    ctl->done = 1u;
+    return;
+  }
+  ctl->dt = dt;
+  ctl->done = 0u;
+  ctl->t = ctl->t + dt;
+  ctl->step += 1;
+  ctl->amax_bits = 0ull;
+}
+
+template <typename R>
+__global__ __launch_bounds__(kStepThreads, SALE_WAVES_STEP) void k_lagrange(RunArgs<R> a) {
+  __shared__ double lds[lagrange_lds_doubles<CH>()];
+  if (a.ctl->done) return;
+  const bool t = lagrange_tile<R, CH>(a, xcd_logical_block(blockIdx.x, gridDim.x), a.ctl->dt, lds);
+  if (t) atomicOr(&a.ctl->status, SALE_FLAG_TANGLE);
+}
+
+template <typename R>
+__global__ __launch_bounds__(kStepThreads, SALE_WAVES_STEP) void k_remap(RunArgs<R> a) {
+  __shared__ double lds[remap_lds_doubles<CH>()];
+  const int b = xcd_logical_block(blockIdx.x, gridDim.x);
+  if (a.ctl->done) {
+    copy_tile<R, CH>(a, b);
+    return;
+  }
+  double amax;
+  bool bad;
+  remap_tile<R, CH>(a, b, lds, &amax, &bad);
+  block_max_to_ctl<kStepThreads>(a.ctl, amax, bad);
+}
+
+// ---------------------------------------------------------------------------------
+// initial states, signal speed of a state, diagnostics, export
+// ---------------------------------------------------------------------------------
+__device__ __forceinline__ void cell_ijk(const Mesh &m, int64_t c, int &i, int &j, int &k) {
+  i = (int)(c % m.nx);
+  const int64_t r = c / m.nx;
+  j = (int)(r % m.ny);
+  k = (int)(r / m.ny);
+}
+__device__ __forceinline__ void node_ijk(const Mesh &m, int64_t n, int &i, int &j, int &k) {
+  i = (int)(n % (m.nx + 1));
+  const int64_t r = n / (m.nx + 1);
+  j = (int)(r % (m.ny + 1));
+  k = (int)(r / (m.ny + 1));
+}
+
+// sum_p S_{c,p} . u_p of cell (i,j,k), as edge differences, in R
+template <typename R>
+__device__ __forceinline__ R corner_div(const Mesh &m, const State<R> &s, int i, int j, int k) {
+  const int64_t sy = m.nx + 1, sz = (int64_t)(m.nx + 1) * (m.ny + 1);
+  const int64_t n0 = nidx(m, i, j, k);
+  R sx = 0, syy = 0, szz = 0;
+#pragma unroll
+  for (int t2 = 0; t2 < 2; t2++)
+#pragma unroll
+    for (int t1 = 0; t1 < 2; t1++) {
+      sx += s.u[n0 + 1 + t1 * sy + t2 * sz] - s.u[n0 + t1 * sy + t2 * sz];
+      syy += s.v[n0 + sy + t1 + t2 * sz] - s.v[n0 + t1 + t2 * sz];
+      szz += s.w[n0 + sz + t1 + t2 * sy] - s.w[n0 + t1 + t2 * sy];
+    }
+  return R(m.ax) * sx + R(m.ay) * syy + R(m.az) * szz;
+}
+
+template <typename R>
+__global__ __launch_bounds__(TPB) void k_signal(Mesh m, Ctl *ctl, State<R> s) {
+  const int64_t c = blockIdx.x * (int64_t)TPB + threadIdx.x;
+  double a = 0.0;
+  bool bad = false;
+  if (c < m.ncell) {
+    int i, j, k;
+    cell_ijk(m, c, i, j, k);
+    const R D = corner_div(m, s, i, j, k) / R(m.V0);
+    R smax = 0;
+    for (int cc = 0; cc < 2; cc++)
+      for (int b = 0; b < 2; b++)
+        for (int aa = 0; aa < 2; aa++) {
+          const int64_t n = nidx(m, i + aa, j + b, k + cc);
+          const R sp = sqrt(s.u[n] * s.u[n] + s.v[n] * s.v[n] + s.w[n] * s.w[n]);
+          if (!isfinite(sp)) bad = true;
+          smax = fmax(smax, sp);
+        }
+    const R rho = s.rho[c], e = s.e[c];
+    const R sa = signal_from(m, D, e, smax);
+    a = (double)sa;
+    if (!(rho > R(0)) || !isfinite(rho) || !(e >= R(0)) || !isfinite(e) || !isfinite(sa)) bad = true;
+  }
+  block_max_to_ctl<TPB>(ctl, a, bad);
+}
+
+__global__ void k_ctl_init(Ctl *ctl, double t0, long long step0, double t_end) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  ctl->t = t0;
+  ctl->dt = 0.0;
+  ctl->t_end = t_end;
+  ctl->dt_next = 0.0;
+  ctl->amax_bits = 0ull;
+  ctl->step = step0;
+  ctl->status = 0u;
+  ctl->done = 0u;
+  ctl->totals[0] = ctl->totals[1] = 0.0;
+  ctl->tiles_done = 0u;
+  ctl->phase = 0u;
+  ctl->step_target = 0;
+}
+
+__global__ void k_set_t_end(Ctl *ctl, double t_end) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) ctl->t_end = t_end;
+}
+
+template <typename R>
+__global__ __launch_bounds__(TPB) void k_init_cells_sod(Mesh m, State<R> s, double xs, double rL, double pL,
+                                                       double rR, double pR) {
+  const int64_t c = blockIdx.x * (int64_t)TPB + threadIdx.x;
+  if (c >= m.ncell) return;
+  int i, j, k;
+  cell_ijk(m, c, i, j, k);
+  const double xc = m.lo[0] + (i + 0.5) * m.dx;
+  const bool left = xc < xs;
+  const double r = left ? rL : rR;
+  s.rho[c] = R(r);
+  s.e[c] = R((left ? pL : pR) / ((m.gamma - 1.0) * r));
+}
+
+template <typename R>
+__global__ __launch_bounds__(TPB) void k_init_cells_sedov(Mesh m, State<R> s, double r0, double p0,
+                                                         double edep) {
+  const int64_t c = blockIdx.x * (int64_t)TPB + threadIdx.x;
+  if (c >= m.ncell) return;
+  s.rho[c] = R(r0);
+  s.e[c] = R(c == 0 ? edep / (r0 * m.V0) : p0 / ((m.gamma - 1.0) * r0));
+}
+
+template <typename R>
+__global__ __launch_bounds__(TPB) void k_zero_nodes(Mesh m, State<R> s) {
+  const int64_t n = blockIdx.x * (int64_t)TPB + threadIdx.x;
+  if (n >= m.nnode) return;
+  s.u[n] = s.v[n] = s.w[n] = R(0);
+}
+
+// copy a double array into an R array (user initial data)
+template <typename R>
+__global__ __launch_bounds__(TPB) void k_from_double(const double *src, R *dst, int64_t n) {
+  const int64_t q = blockIdx.x * (int64_t)TPB + threadIdx.x;
+  if (q < n) dst[q] = R(src[q]);
+}
+
+template <typename R>
+__global__ __launch_bounds__(TPB) void k_wall_normals(Mesh m, State<R> s) {
+  const int64_t n = blockIdx.x * (int64_t)TPB + threadIdx.x;
+  if (n >= m.nnode) return;
+  int i, j, k;
+  node_ijk(m, n, i, j, k);
+  if (i == 0 || i == m.nx) s.u[n] = R(0);
+  if (j == 0 || j == m.ny) s.v[n] = R(0);
+  if (k == 0 || k == m.nz) s.w[n] = R(0);
+}
+
+constexpr int TOT_BLOCKS = 1024;
+
+template <typename R>
+__global__ __launch_bounds__(TPB) void k_totals_partial(Mesh m, State<R> s, double *partial) {
+  double sm = 0.0, si = 0.0, sk = 0.0;
+  for (int64_t c = blockIdx.x * (int64_t)TPB + threadIdx.x; c < m.ncell; c += (int64_t)TOT_BLOCKS * TPB) {
+    const double mc = (double)s.rho[c] * m.V0;
+    sm += mc;
+    si += mc * (double)s.e[c];
+  }
+  for (int64_t n = blockIdx.x * (int64_t)TPB + threadIdx.x; n < m.nnode; n += (int64_t)TOT_BLOCKS * TPB) {
+    int i, j, k;
+    node_ijk(m, n, i, j, k);
+    double ms = 0.0;
+    for (int cc = -1; cc <= 0; cc++)
+      for (int b = -1; b <= 0; b++)
+        for (int a = -1; a <= 0; a++)
+          if (cell_in(m, i + a, j + b, k + cc)) ms += (double)s.rho[cidx(m, i + a, j + b, k + cc)] * m.V0;
+    const double u = s.u[n], v = s.v[n], w = s.w[n];
+    sk += 0.5 * (0.125 * ms) * (u * u + v * v + w * w);
+  }
+  __shared__ double red[3][TPB / 64];
+  sm = wave_sum(sm);
+  si = wave_sum(si);
+  sk = wave_sum(sk);
+  if ((threadIdx.x & 63) == 0) {
+    red[0][threadIdx.x >> 6] = sm;
+    red[1][threadIdx.x >> 6] = si;
+    red[2][threadIdx.x >> 6] = sk;
+  }
+  __syncthreads();
+  if (threadIdx.x < 3) {
+    double r = 0.0;
+    for (int q = 0; q < TPB / 64; q++) r += red[threadIdx.x][q];
+    partial[threadIdx.x * TOT_BLOCKS + blockIdx.x] = r;
+  }
+}
+
+__global__ __launch_bounds__(TPB) void k_totals_final(Ctl *ctl, const double *partial) {
+  __shared__ double red[3][TPB / 64];
+  double s[3];
+  for (int a = 0; a < 3; a++) {
+    double x = 0.0;
+    for (int b = threadIdx.x; b < TOT_BLOCKS; b += TPB) x += partial[a * TOT_BLOCKS + b];
+    s[a] = wave_sum(x);
+  }
+  if ((threadIdx.x & 63) == 0)
+    for (int a = 0; a < 3; a++) red[a][threadIdx.x >> 6] = s[a];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double r[3] = {0.0, 0.0, 0.0};
+    for (int a = 0; a < 3; a++)
+      for (int q = 0; q < TPB / 64; q++) r[a] += red[a][q];
+    ctl->totals[0] = r[0];
+    ctl->totals[1] = r[1] + r[2];
+  }
+}
+
+// field `which` as double: 0 rho, 1 e, 2 p, 3 q, 4 u, 5 v, 6 w
+template <typename R>
+__global__ __launch_bounds__(TPB) void k_export(Mesh m, State<R> s, int which, double *out) {
+  const int64_t q = blockIdx.x * (int64_t)TPB + threadIdx.x;
+  if (which >= 4) {
+    if (q >= m.nnode) return;
+    const R *src = which == 4 ? s.u : (which == 5 ? s.v : s.w);
+    out[q] = (double)src[q];
+    return;
+  }
+  if (q >= m.ncell) return;
+  const R rho = s.rho[q], e = s.e[q];
+  if (which == 0) {
+    out[q] = (double)rho;
+  } else if (which == 1) {
+    out[q] = (double)e;
+  } else if (which == 2) {
+    out[q] = (double)((R(m.gamma) - R(1)) * rho * e);
+  } else {
+    int i, j, k;
+    cell_ijk(m, q, i, j, k);
+    const R gm = R(m.gamma), h = R(m.h);
+    const R cs = sqrt(gm * (gm - R(1)) * fmax(e, R(0)));
+    const R D = corner_div(m, s, i, j, k) / R(m.V0);
+    R qv = 0;
+    if (D < R(0)) {
+      const R hd = h * D;
+      qv = rho * (R(m.cq) * hd * hd + R(m.cl) * cs * h * fabs(D));
+    }
+    out[q] = (double)qv;
+  }
+}
+
+inline unsigned blocks(int64_t n) { return (unsigned)((n + TPB - 1) / TPB); }
+
+// z segments so that tiles x segments fills the chip a few times over
+Grid2 make_grid(int nx, int ny, int nplanes, int tile_x, int tile_y, int target_blocks) {
+  Grid2 g;
+  g.tx = (nx + tile_x - 1) / tile_x;
+  g.ty = (ny + tile_y - 1) / tile_y;
+  const int tiles = g.tx * g.ty;
+  int nseg = (target_blocks + tiles / 2) / tiles;
+  const int maxseg = nplanes / 8 > 1 ? nplanes / 8 : 1;  // keep >= 8 planes per segment
+  if (nseg > maxseg) nseg = maxseg;
+  if (nseg < 1) nseg = 1;
+  g.seglen = (nplanes + nseg - 1) / nseg;
+  g.nseg = (nplanes + g.seglen - 1) / g.seglen;
+  return g;
+}
+
+}  // namespace
+
+Grid2 grid_lagrange(const Mesh &m, int target_blocks) {
+  return make_grid(m.nx, m.ny, m.nz, 32 - 3, CH - 3, target_blocks);
+}
+Grid2 grid_remap(const Mesh &m, int target_blocks) {
+  return make_grid(m.nx, m.ny, m.nz, 32 - 4, CH - 4, target_blocks);
+}
+
+// ---- workspace layout -----------------------------------------------------------------
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+template <typename R>
+size_t workspace_bytes(const Mesh &m) {
+  const size_t cR = align256((size_t)m.ncell * sizeof(R)), nR = align256((size_t)m.nnode * sizeof(R));
+  const size_t cD = align256((size_t)m.ncell * sizeof(double));
+  const size_t sD = align256((size_t)(m.ncell > m.nnode ? m.ncell : m.nnode) * sizeof(double));
+  // ctl | 2 states | u' | rho^L, e^L | 3 swept volumes | partials | scratch
+  return align256(sizeof(Ctl)) + 2 * (2 * cR + 3 * nR) + 3 * nR + 2 * cR + 3 * cD +
+         align256(3 * TOT_BLOCKS * sizeof(double)) + sD;
+}
+
+template <typename R>
+void layout(const Mesh &m, void *ws, Ctl **ctl, Work<R> *w) {
+  const size_t cR = align256((size_t)m.ncell * sizeof(R)), nR = align256((size_t)m.nnode * sizeof(R));
+  const size_t cD = align256((size_t)m.ncell * sizeof(double));
+  const size_t sD = align256((size_t)(m.ncell > m.nnode ? m.ncell : m.nnode) * sizeof(double));
+  char *p = (char *)ws;
+  *ctl = (Ctl *)p;
+  p += align256(sizeof(Ctl));
+  auto takeR = [&](size_t b) {
+    R *r = (R *)p;
+    p += b;
+    return r;
+  };
+  auto takeD = [&](size_t b) {
+    double *r = (double *)p;
+    p += b;
+    return r;
+  };
+  for (int a = 0; a < 2; a++) {
+    w->s[a].rho = takeR(cR);
+    w->s[a].e = takeR(cR);
+    w->s[a].u = takeR(nR);
+    w->s[a].v = takeR(nR);
+    w->s[a].w = takeR(nR);
+  }
+  w->up = takeR(nR);
+  w->vp = takeR(nR);
+  w->wp = takeR(nR);
+  w->geo.rl = takeR(cR);
+  w->geo.el = takeR(cR);
+  w->geo.dvx = takeD(cD);
+  w->geo.dvy = takeD(cD);
+  w->geo.dvz = takeD(cD);
+  w->partial = takeD(align256(3 * TOT_BLOCKS * sizeof(double)));
+  w->scratch = takeD(sD);
+}
+
+// ---- launchers ----------------------------------------------------------------------------
+template <typename R>
+static hipError_t finish_init(const Mesh &m, Ctl *ctl, const Work<R> &w, double t0, long long step0,
+                              double t_end, hipStream_t s) {
+  hipLaunchKernelGGL(k_ctl_init, dim3(1), dim3(64), 0, s, ctl, t0, step0, t_end);
+  hipLaunchKernelGGL(k_signal<R>, dim3(blocks(m.ncell)), dim3(TPB), 0, s, m, ctl, w.s[0]);
+  return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_init_sod(const Mesh &m, Ctl *ctl, const Work<R> &w, const double sod[5], double t0,
+                           long long step0, double t_end, hipStream_t s) {
+  hipLaunchKernelGGL(k_init_cells_sod<R>, dim3(blocks(m.ncell)), dim3(TPB), 0, s, m, w.s[0], sod[0], sod[1],
+                     sod[2], sod[3], sod[4]);
+  hipLaunchKernelGGL(k_zero_nodes<R>, dim3(blocks(m.nnode)), dim3(TPB), 0, s, m, w.s[0]);
+  return finish_init(m, ctl, w, t0, step0, t_end, s);
+}
+
+template <typename R>
+hipError_t launch_init_sedov(const Mesh &m, Ctl *ctl, const Work<R> &w, const double sedov[3], double t0,
+                             long long step0, double t_end, hipStream_t s) {
+  hipLaunchKernelGGL(k_init_cells_sedov<R>, dim3(blocks(m.ncell)), dim3(TPB), 0, s, m, w.s[0], sedov[0],
+                     sedov[1], sedov[2]);
+  hipLaunchKernelGGL(k_zero_nodes<R>, dim3(blocks(m.nnode)), dim3(TPB), 0, s, m, w.s[0]);
+  return finish_init(m, ctl, w, t0, step0, t_end, s);
+}
+
+template <typename R>
+hipError_t launch_init_user(const Mesh &m, Ctl *ctl, const Work<R> &w, const double *const src[5],
+                            bool on_device, double t0, long long step0, double t_end, hipStream_t s) {
+  R *dst[5] = {w.s[0].rho, w.s[0].e, w.s[0].u, w.s[0].v, w.s[0].w};
+  for (int a = 0; a < 5; a++) {
+    const int64_t n = a < 2 ? m.ncell : m.nnode;
+    const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    hipError_t e = hipMemcpyAsync(w.scratch, src[a], (size_t)n * sizeof(double), kind, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_from_double<R>, dim3(blocks(n)), dim3(TPB), 0, s, (const double *)w.scratch, dst[a], n);
+    // a host source must not be touched after return, and the scratch array
+    // is reused by the next field: host copies wait here
+    if (!on_device && (e = hipStreamSynchronize(s)) != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_wall_normals<R>, dim3(blocks(m.nnode)), dim3(TPB), 0, s, m, w.s[0]);
+  return finish_init(m, ctl, w, t0, step0, t_end, s);
+}
+
+hipError_t launch_set_t_end(Ctl *ctl, double t_end, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_t_end, dim3(1), dim3(64), 0, s, ctl, t_end);
+  return hipGetLastError();
+}
+
+template <typename R>
+RunArgs<R> run_args(const Mesh &m, Ctl *ctl, const Work<R> &w, int cur, int target_blocks) {
+  RunArgs<R> a;
+  a.m = m;
+  a.ctl = ctl;
+  a.cur = w.s[cur];
+  a.nxt = w.s[1 - cur];
+  a.up = w.up;
+  a.vp = w.vp;
+  a.wp = w.wp;
+  a.geo = w.geo;
+  a.ga = grid_lagrange(m, target_blocks);
+  a.gb = grid_remap(m, target_blocks);
+  return a;
+}
+
+template <typename R>
+hipError_t launch_step(const Mesh &m, Ctl *ctl, const Work<R> &w, int cur, hipStream_t s) {
+  const RunArgs<R> a = run_args<R>(m, ctl, w, cur, 3072);
+  hipLaunchKernelGGL(k_begin, dim3(1), dim3(64), 0, s, m, ctl);
+  hipLaunchKernelGGL(k_lagrange<R>, dim3(a.ga.blocks()), dim3(kStepThreads), 0, s, a);
+  hipLaunchKernelGGL(k_remap<R>, dim3(a.gb.blocks()), dim3(kStepThreads), 0, s, a);
+  return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_totals(const Mesh &m, Ctl *ctl, const Work<R> &w, int cur, hipStream_t s) {
+  hipLaunchKernelGGL(k_totals_partial<R>, dim3(TOT_BLOCKS), dim3(TPB), 0, s, m, w.s[cur], w.partial);
+  hipLaunchKernelGGL(k_totals_final, dim3(1), dim3(TPB), 0, s, ctl, (const double *)w.partial);
+  return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_export(const Mesh &m, const Work<R> &w, int cur, int which, double *out, hipStream_t s) {
+  const int64_t n = which >= 4 ? m.nnode : m.ncell;
+  hipLaunchKernelGGL(k_export<R>, dim3(blocks(n)), dim3(TPB), 0, s, m, w.s[cur], which, out);
+  return hipGetLastError();
+}
+
+#define SALE_INSTANTIATE(R)                                                                              \
+  template size_t workspace_bytes<R>(const Mesh &);                                                      \
+  template void layout<R>(const Mesh &, void *, Ctl **, Work<R> *);                                      \
+  template hipError_t launch_init_sod<R>(const Mesh &, Ctl *, const Work<R> &, const double[5], double,  \
+                                         long long, double, hipStream_t);                                \
+  template hipError_t launch_init_sedov<R>(const Mesh &, Ctl *, const Work<R> &, const double[3], double, \
+                                           long long, double, hipStream_t);                              \
+  template hipError_t launch_init_user<R>(const Mesh &, Ctl *, const Work<R> &, const double *const[5],  \
+                                          bool, double, long long, double, hipStream_t);                 \
+  template RunArgs<R> run_args<R>(const Mesh &, Ctl *, const Work<R> &, int, int);                       \
+  template hipError_t launch_step<R>(const Mesh &, Ctl *, const Work<R> &, int, hipStream_t);            \
+  template hipError_t launch_totals<R>(const Mesh &, Ctl *, const Work<R> &, int, hipStream_t);          \
+  template hipError_t launch_export<R>(const Mesh &, const Work<R> &, int, int, double *, hipStream_t);
+SALE_INSTANTIATE(double)
+SALE_INSTANTIATE(float)
+
+}  // namespace sale

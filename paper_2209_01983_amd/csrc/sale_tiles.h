@@ -1,0 +1,657 @@
+// sale_tiles.h -- the two z-marching tile functions of the SALE step, shared
+// by the single-run kernels and the persistent multi-run kernel.
+//
+// One step is the Lagrangian phase on the structured hex mesh followed by the
+// Eulerian rezone and donor-cell advection back to the fixed mesh (ScalSALE
+// Sec. I-D and Table I: "Lagrangian rezoning", "Eulerian rezoning",
+// "Advection"), with the ideal-gas EoS (Sec. I-C/I-D), cell-centred rho/e/p/q
+// and vertex velocities (Sec. III-B/III-C) and density as mass over volume
+// (Sec. III-A). The paper prints no scheme equations; the tiles compute the
+// scheme of the project's FP64 oracle (its steps O1..O12):
+//
+//   lagrange_tile  O1, O2, O4..O8  EOS, divergence, viscosity, acoustic
+//                  predictor P*, atomic-free gather of corner forces, u',
+//                  walls, compatible energy e^L, exact swept volumes, V^L, rho^L
+//   remap_tile     O9..O11 and the next O3 reduction: donor-cell face fluxes,
+//                  M, rho^{n+1}, e^pre, dual-mesh momentum / KE remap,
+//                  u^{n+1}, KE fix, e^{n+1}, next signal speed
+//
+// A tile is a 32 x CH grid of (x, y) columns, one thread per column, marched
+// along z over one z segment one plane at a time. A plane's values live in
+// LDS while its x/y neighbours need them; values a column needs again one or
+// two planes later stay in that column's registers; global loads run one
+// plane ahead. The hand-off between the two tiles is u' (per node) and the
+// Lagrangian cell results rho^L, e^L and three lower-face swept volumes,
+// whose faces need only the cell's own nodes, so no geometry is computed
+// twice. Nothing scatters, so results do not depend on scheduling.
+//
+// Precision: R is the bulk type (double, or float for SALE_MIXED32). Node
+// displacements, swept volumes, volume differences and V^L are always
+// computed in double, as are dt and the signal-speed reduction.
+#pragma once
+
+#include "sale_device.h"
+
+namespace sale {
+
+// ---- O5: acoustic predictor P* of one cell (O2, O4 folded in) ----------------
+template <typename R>
+__device__ __forceinline__ R predict_ps(const Mesh &m, R rho, R e, R D, R dt, bool &tangle) {
+  const R V0 = R(m.V0), gm = R(m.gamma), h = R(m.h);
+  const R mc = rho * V0;
+  const R p = (gm - R(1)) * rho * e;
+  const R cs = sqrt(gm * (gm - R(1)) * fmax(e, R(0)));
+  R q = R(0);
+  if (D < R(0)) {
+    const R hd = h * D;
+    q = rho * (R(m.cq) * hd * hd + R(m.cl) * cs * h * fabs(D));
+  }
+  const R dVs = R(0.5) * dt * V0 * D;
+  const R Vs = V0 + dVs;
+  if (!(Vs > R(0))) {
+    tangle = true;
+    return R(0);
+  }
+  const R rs = mc / Vs;
+  const R es = e - (p + q) * dVs / mc;
+  return (gm - R(1)) * rs * es + q;
+}
+
+// ---- O3: signal speed from a cell's divergence, energy and node speeds --------
+template <typename R>
+__device__ __forceinline__ R signal_from(const Mesh &m, R D, R e, R smax) {
+  const R gm = R(m.gamma);
+  const R cs = sqrt(gm * (gm - R(1)) * fmax(e, R(0)));
+  return cs + smax + R(4) * R(m.cq) * R(m.h) * fmax(-D, R(0));
+}
+
+__device__ __forceinline__ void tile_of(const Grid2 &g, int b, int &tx, int &ty, int &seg) {
+  tx = b % g.tx;
+  const int r = b / g.tx;
+  ty = r % g.ty;
+  seg = r / g.ty;
+}
+
+// LDS doubles needed by each tile function for a 32 x CH tile
+template <int CH>
+constexpr int lagrange_lds_doubles() {
+  return 13 * 32 * CH;
+}
+template <int CH>
+constexpr int remap_lds_doubles() {
+  return 18 * 32 * CH;
+}
+
+// ---------------------------------------------------------------------------------
+// lagrange_tile: the Lagrangian phase of one tile
+// ---------------------------------------------------------------------------------
+// Column (ci, cj) is node column / cell column (X0 + ci - 1, Y0 + cj - 1). The
+// tile owns cells [X0, X0+TX) x [Y0, Y0+TY) of its z segment and the matching
+// nodes. Iteration k:
+//   P1  u of node plane k+1 into LDS (loaded one iteration earlier)
+//   P2  D and P* of cell plane k (halo 1): the divergence sums edge
+//       differences of u over the cell's two node planes; each node plane's
+//       half is formed once and carried one plane
+//   P3  u' and delta = dt (u + u')/2 of node plane k: gather of P* over the
+//       node's 8 cells as a per-plane sum carried one plane            (LDS)
+//   P4  swept volumes of the faces of cell plane k-1 (they need delta on node
+//       planes k-1 and k only) and its compatible-energy work
+//   P5  V^L, rho^L, e^L of cell plane k-1; hand-off to remap_tile
+// Returns true if a tangled cell was seen.
+template <typename R, int CH>
+__device__ bool lagrange_tile(const RunArgs<R> &a, int b, double dtd, double *lds) {
+  constexpr int CW = 32, NTH = CW * CH, TX = CW - 3, TY = CH - 3;
+  const Mesh &m = a.m;
+  const State<R> &cur = a.cur;
+  int tx, ty, seg;
+  tile_of(a.ga, b, tx, ty, seg);
+  const int ci = threadIdx.x % CW, cj = threadIdx.x / CW;
+  const int gi = tx * TX + ci - 1, gj = ty * TY + cj - 1;
+  const int Z0 = seg * a.ga.seglen;
+  const bool lastseg = seg == a.ga.nseg - 1;
+  const int Z1 = lastseg ? m.nz : Z0 + a.ga.seglen;  // cell planes [Z0, Z1)
+  const int NZ1 = lastseg ? m.nz + 1 : Z1;           // node planes [Z0, NZ1)
+  const bool ncol = gi >= 0 && gi <= m.nx && gj >= 0 && gj <= m.ny;
+  const bool inner = ci < CW - 1 && cj < CH - 1;  // has the +x and +y neighbour column
+  const bool ccol = inner && gi >= 0 && gi < m.nx && gj >= 0 && gj < m.ny;
+  const bool nodecol = ci >= 1 && cj >= 1 && inner;  // u' computed here
+  const bool own_node = ncol && ci >= 1 && cj >= 1 && (ci <= TX || gi == m.nx) && (cj <= TY || gj == m.ny);
+  const bool own_cell = ci >= 1 && cj >= 1 && ci <= TX && cj <= TY && gi < m.nx && gj < m.ny;
+
+  // LDS: bulk planes as R, delta ring and swept volumes as double
+  R(*sU)[CH][CW] = reinterpret_cast<R(*)[CH][CW]>(lds);                // [3]
+  R(*sP)[CW] = reinterpret_cast<R(*)[CW]>(lds + 3 * CH * CW);          // P*
+  R(*sM)[CW] = reinterpret_cast<R(*)[CW]>(lds + 4 * CH * CW);          // m
+  double(*sD)[3][CH][CW] = reinterpret_cast<double(*)[3][CH][CW]>(lds + 5 * CH * CW);  // [2][3]
+  double(*sVX)[CW] = reinterpret_cast<double(*)[CW]>(lds + 11 * CH * CW);
+  double(*sVY)[CW] = reinterpret_cast<double(*)[CW]>(lds + 12 * CH * CW);
+
+  for (int q = threadIdx.x; q < 2 * 3 * CH * CW; q += NTH) (&sD[0][0][0][0])[q] = 0.0;
+
+  const R dt = R(dtd);
+  const R ax = R(m.ax), ay = R(m.ay), az = R(m.az), V0 = R(m.V0);
+  R pxu = 0, pyu = 0, pzu = 0;       // node-plane halves of D (plane k)
+  R fx = 0, fy = 0, fz = 0, mk = 0;  // 4-cell sums of P*, m of cell plane k-1
+  R u0 = 0, v0 = 0, w0 = 0;          // own column's u at node plane k
+  double pxd = 0.0, pyd = 0.0, pzd = 0.0;  // node-plane halves of the work (plane k-1)
+  double dvz_lo = 0.0;                     // z-face swept volume at node plane k-1
+  R ps1 = 0, e1 = 0, m1 = 0;               // P*, e, m of cell plane k-1
+  bool tangle = false;
+
+  // global loads run one plane ahead
+  R fu = 0, fv = 0, fw = 0, frho = 0, fe = 0;
+  auto fetch = [&](int k) {
+    fu = fv = fw = frho = fe = R(0);
+    if (ncol && k + 1 >= 0 && k + 1 <= m.nz) {
+      const int64_t n = nidx(m, gi, gj, k + 1);
+      fu = cur.u[n];
+      fv = cur.v[n];
+      fw = cur.w[n];
+    }
+    if (ccol && k >= 0 && k < m.nz) {
+      const int64_t c = cidx(m, gi, gj, k);
+      frho = cur.rho[c];
+      fe = cur.e[c];
+    }
+  };
+  fetch(Z0 - 2);
+
+  for (int k = Z0 - 2; k <= Z1; k++) {
+    // ---- P1 ----
+    const R un = fu, vn = fv, wn = fw, rho_k = frho, e_k = fe;
+    fetch(k + 1);
+    sU[0][cj][ci] = un;
+    sU[1][cj][ci] = vn;
+    sU[2][cj][ci] = wn;
+    __syncthreads();
+    // ---- P2 ----
+    R ps = 0, mc = 0;
+    {
+      R qxu = 0, qyu = 0, qzu = 0;
+      if (inner) {
+        qxu = (sU[0][cj][ci + 1] - sU[0][cj][ci]) + (sU[0][cj + 1][ci + 1] - sU[0][cj + 1][ci]);
+        qyu = (sU[1][cj + 1][ci] - sU[1][cj][ci]) + (sU[1][cj + 1][ci + 1] - sU[1][cj][ci + 1]);
+        qzu = ((sU[2][cj][ci] + sU[2][cj][ci + 1]) + sU[2][cj + 1][ci]) + sU[2][cj + 1][ci + 1];
+      }
+      if (ccol && k >= 0 && k < m.nz) {
+        mc = rho_k * V0;
+        const R D = ((ax * (pxu + qxu) + ay * (pyu + qyu)) + az * (qzu - pzu)) / V0;
+        bool t = false;
+        ps = predict_ps(m, rho_k, e_k, D, dt, t);
+        if (t && own_cell && k >= Z0 && k < Z1) tangle = true;
+      }
+      pxu = qxu;
+      pyu = qyu;
+      pzu = qzu;
+    }
+    sP[cj][ci] = ps;
+    sM[cj][ci] = mc;
+    __syncthreads();
+    // ---- P3 ----
+    {
+      double d0 = 0.0, d1 = 0.0, d2 = 0.0;
+      if (nodecol) {
+        const R gx = (sP[cj][ci - 1] - sP[cj][ci]) + (sP[cj - 1][ci - 1] - sP[cj - 1][ci]);
+        const R gy = (sP[cj - 1][ci] - sP[cj][ci]) + (sP[cj - 1][ci - 1] - sP[cj][ci - 1]);
+        const R gz = ((sP[cj][ci] + sP[cj][ci - 1]) + sP[cj - 1][ci]) + sP[cj - 1][ci - 1];
+        const R gm = ((sM[cj][ci] + sM[cj][ci - 1]) + sM[cj - 1][ci]) + sM[cj - 1][ci - 1];
+        if (ncol && k >= 0 && k <= m.nz) {
+          // node k is the +z corner of the cells of plane k-1, the -z corner of plane k
+          const R Fx = ax * (fx + gx), Fy = ay * (fy + gy), Fz = az * (fz - gz);
+          const R mp = R(0.125) * (mk + gm);
+          R u1 = u0 + dt * Fx / mp;
+          R v1 = v0 + dt * Fy / mp;
+          R w1 = w0 + dt * Fz / mp;
+          if (gi == 0 || gi == m.nx) u1 = R(0);
+          if (gj == 0 || gj == m.ny) v1 = R(0);
+          if (k == 0 || k == m.nz) w1 = R(0);
+          if (own_node && k >= Z0 && k < NZ1) {
+            const int64_t n = nidx(m, gi, gj, k);
+            a.up[n] = u1;
+            a.vp[n] = v1;
+            a.wp[n] = w1;
+          }
+          d0 = dtd * (0.5 * ((double)u0 + (double)u1));
+          d1 = dtd * (0.5 * ((double)v0 + (double)v1));
+          d2 = dtd * (0.5 * ((double)w0 + (double)w1));
+        }
+        fx = gx;
+        fy = gy;
+        fz = gz;
+        mk = gm;
+      }
+      sD[k & 1][0][cj][ci] = d0;
+      sD[k & 1][1][cj][ci] = d1;
+      sD[k & 1][2][cj][ci] = d2;
+      u0 = un;
+      v0 = vn;
+      w0 = wn;
+    }
+    __syncthreads();
+    // ---- P4: faces and work of cell plane k-1 ----
+    const int cp = k - 1;
+    const bool plane_ok = cp >= 0 && cp < m.nz && k > Z0 - 2;
+    double work = 0.0, dvz_up = 0.0;
+    {
+      const double(*A)[CH][CW] = sD[cp & 1];  // node plane k-1
+      const double(*B)[CH][CW] = sD[k & 1];   // node plane k
+      double qxd = 0.0, qyd = 0.0, qzd = 0.0;
+      if (inner) {
+        qxd = (B[0][cj][ci + 1] - B[0][cj][ci]) + (B[0][cj + 1][ci + 1] - B[0][cj + 1][ci]);
+        qyd = (B[1][cj + 1][ci] - B[1][cj][ci]) + (B[1][cj + 1][ci + 1] - B[1][cj][ci + 1]);
+        qzd = ((B[2][cj][ci] + B[2][cj][ci + 1]) + B[2][cj + 1][ci]) + B[2][cj + 1][ci + 1];
+      }
+      // work = sum_p S_cp . delta_p (= dt sum S.u_bar) of cell plane k-1
+      work = (m.ax * (pxd + qxd) + m.ay * (pyd + qyd)) + m.az * (qzd - pzd);
+      pxd = qxd;
+      pyd = qyd;
+      pzd = qzd;
+      double vx = 0.0, vy = 0.0;
+      // x face at node column gi between cells gi-1, gi; corners (s: y, t: z)
+      if (plane_ok && ci >= 1 && ci <= TX + 1 && cj >= 1 && cj <= TY && gi >= 1 && gi <= m.nx - 1 && gj >= 0 &&
+          gj < m.ny) {
+        const double d0[3] = {A[0][cj][ci], A[1][cj][ci], A[2][cj][ci]};
+        const double d1[3] = {A[0][cj + 1][ci], A[1][cj + 1][ci], A[2][cj + 1][ci]};
+        const double d2[3] = {B[0][cj][ci], B[1][cj][ci], B[2][cj][ci]};
+        const double d3[3] = {B[0][cj + 1][ci], B[1][cj + 1][ci], B[2][cj + 1][ci]};
+        vx = swept_volume(d0, d1, d2, d3, m.dy, m.dz);
+      }
+      // y face at node row gj between cells gj-1, gj; corners (s: z, t: x); comps (y, z, x)
+      if (plane_ok && ci >= 1 && ci <= TX && cj >= 1 && cj <= TY + 1 && gj >= 1 && gj <= m.ny - 1 && gi >= 0 &&
+          gi < m.nx) {
+        const double d0[3] = {A[1][cj][ci], A[2][cj][ci], A[0][cj][ci]};
+        const double d1[3] = {B[1][cj][ci], B[2][cj][ci], B[0][cj][ci]};
+        const double d2[3] = {A[1][cj][ci + 1], A[2][cj][ci + 1], A[0][cj][ci + 1]};
+        const double d3[3] = {B[1][cj][ci + 1], B[2][cj][ci + 1], B[0][cj][ci + 1]};
+        vy = swept_volume(d0, d1, d2, d3, m.dz, m.dx);
+      }
+      // z face at node plane k between cells k-1, k; corners (s: x, t: y); comps (z, x, y)
+      if (own_cell && k >= 1 && k <= m.nz - 1) {
+        const double d0[3] = {B[2][cj][ci], B[0][cj][ci], B[1][cj][ci]};
+        const double d1[3] = {B[2][cj][ci + 1], B[0][cj][ci + 1], B[1][cj][ci + 1]};
+        const double d2[3] = {B[2][cj + 1][ci], B[0][cj + 1][ci], B[1][cj + 1][ci]};
+        const double d3[3] = {B[2][cj + 1][ci + 1], B[0][cj + 1][ci + 1], B[1][cj + 1][ci + 1]};
+        dvz_up = swept_volume(d0, d1, d2, d3, m.dx, m.dy);
+      }
+      sVX[cj][ci] = vx;
+      sVY[cj][ci] = vy;
+    }
+    __syncthreads();
+    // ---- P5: V^L, rho^L, e^L of cell plane k-1 ----
+    if (own_cell && plane_ok && cp >= Z0 && cp < Z1) {
+      const double VL =
+          m.V0 + (((sVX[cj][ci + 1] - sVX[cj][ci]) + (sVY[cj + 1][ci] - sVY[cj][ci])) + (dvz_up - dvz_lo));
+      double rl = 0.0;
+      if (!(VL > 0.0))
+        tangle = true;
+      else
+        rl = (double)m1 / VL;
+      const int64_t c = cidx(m, gi, gj, cp);
+      a.geo.rl[c] = R(rl);
+      a.geo.el[c] = R((double)e1 - (double)ps1 * work / (double)m1);
+      a.geo.dvx[c] = sVX[cj][ci];
+      a.geo.dvy[c] = sVY[cj][ci];
+      a.geo.dvz[c] = dvz_lo;
+    }
+    dvz_lo = dvz_up;
+    ps1 = ps;
+    e1 = e_k;
+    m1 = mc;
+  }
+  return tangle;
+}
+
+// ---------------------------------------------------------------------------------
+// remap_tile: the Eulerian remap (O9..O11) and the next signal speed (O3)
+// ---------------------------------------------------------------------------------
+// Column (ci, cj) is node column / cell column (X0 + ci - 2, Y0 + cj - 2). The
+// tile owns cells [X0, X0+TX) x [Y0, Y0+TY) of its z segment and the matching
+// nodes. Iteration c:
+//   P1  Lagrangian results of cell plane c+1 (halo 2 below, 1 above) and u'
+//       of node plane c+1 into LDS (loaded one iteration earlier)
+//   P2  donor-cell fluxes of its x/y faces and of the z face at node plane c+1
+//   P3  M, rho^{n+1}, e^pre of cell plane c; net x/y fluxes of plane c+1
+//   P4  dual fluxes (1/8 of the adjacent cells' face fluxes) and nodal masses
+//       of node plane c
+//   P5  momentum / kinetic-energy remap of node plane c: u^{n+1}, KE defect
+//   P6  KE fix, e^{n+1} and signal speed of cell plane c-1
+// u' is kept in a 3-plane LDS ring (node planes c-1, c, c+1).
+// Writes the new state; returns the tile's largest signal speed in *amax and
+// whether an owned cell or node was inadmissible in *bad.
+template <typename R, int CH>
+__device__ void remap_tile(const RunArgs<R> &a, int b, double *lds, double *amax_out, bool *bad_out) {
+  constexpr int CW = 32, NTH = CW * CH, TX = CW - 4, TY = CH - 4;
+  const Mesh &m = a.m;
+  int tx, ty, seg;
+  tile_of(a.gb, b, tx, ty, seg);
+  const int ci = threadIdx.x % CW, cj = threadIdx.x / CW;
+  const int gi = tx * TX + ci - 2, gj = ty * TY + cj - 2;
+  const int Z0 = seg * a.gb.seglen;
+  const bool lastseg = seg == a.gb.nseg - 1;
+  const int Z1 = lastseg ? m.nz : Z0 + a.gb.seglen;  // cell planes [Z0, Z1)
+  const int NZ1 = lastseg ? m.nz + 1 : Z1;           // node planes [Z0, NZ1)
+  const bool own_cell = ci >= 2 && cj >= 2 && ci < 2 + TX && cj < 2 + TY && gi < m.nx && gj < m.ny;
+  const bool own_node = ci >= 2 && cj >= 2 && gi <= m.nx && gj <= m.ny && (ci < 2 + TX || gi == m.nx) &&
+                        (cj < 2 + TY || gj == m.ny);
+
+  // LDS slots of 32 x CH values, reused across phases; R slots use the first
+  // half of a double slot when R is float
+  enum {
+    RL = 0, EL = 1, VX = 2, VY = 3,          // Lagrangian results of plane c+1    (P1-P2)
+    MX = 4, EX = 5, MY = 6, EY = 7,          // face fluxes of plane c+1           (P2-P3)
+    SX = 0, SY = 1, MM = 2, MO = 3, SZ = 8,  // flux and mass sums                (P3-P4)
+    PHX = 4, PHY = 5,                        // dual fluxes of node plane c        (P4-P5)
+    UN = 0, SP = 3, DK = 6,                  // 0..2 u^{n+1}; |u^{n+1}|; KE defect (P5-P6)
+    NSLOT = 9
+  };
+  auto RS = [&](int s) { return reinterpret_cast<R(*)[CW]>(lds + s * CH * CW); };
+  double(*sVX)[CW] = reinterpret_cast<double(*)[CW]>(lds + VX * CH * CW);
+  double(*sVY)[CW] = reinterpret_cast<double(*)[CW]>(lds + VY * CH * CW);
+  R(*UPR)[3][CH][CW] = reinterpret_cast<R(*)[3][CH][CW]>(lds + NSLOT * CH * CW);  // [3][3]
+
+  const bool ccol = gi >= 0 && gi < m.nx && gj >= 0 && gj < m.ny;
+  const bool ncol = gi >= 0 && gi <= m.nx && gj >= 0 && gj <= m.ny;
+  const bool r1 = ci >= 1 && cj >= 1 && ci <= CW - 2 && cj <= CH - 2;  // cells and nodes [-1, T]
+  const bool r2 = ci >= 2 && cj >= 2 && ci <= CW - 2 && cj <= CH - 2;  // nodes [0, T]
+  const R V0 = R(m.V0), ax = R(m.ax), ay = R(m.ay), az = R(m.az);
+
+  // column carries: values of cell plane c / node plane c unless noted
+  R rho_c = 0, rl_c = 0, el_c = 0;  // old density, rho^L, e^L
+  R muz_c = 0, epz_c = 0;           // z-face fluxes at node plane c
+  R nxm_c = 0, nxe_c = 0;           // x/y net outflows
+  R ep_c1 = 0;                      // e^pre of cell plane c-1
+  R qx_c = 0, qy_c = 0;             // 2-cell flux sums (dual x/y fluxes)
+  R phx_c = 0, phy_c = 0;           // dual x/y fluxes of node plane c
+  R phz_c1 = 0;                     // z dual flux between node planes c-1 and c
+  R pm_c1 = 0, pr_c1 = 0;           // 4-cell sums of M and m of cell plane c-1
+  R dks1 = 0, sm1 = 0, xn1 = 0, yn1 = 0, zn1 = 0;  // new-state partials of node plane c-1
+  double amax = 0.0;
+  bool bad = false;
+
+  // global loads run one plane ahead
+  R f_rl = 0, f_el = 0, f_rho = 0, f_u = 0, f_v = 0, f_w = 0;
+  double f_vx = 0, f_vy = 0, f_vz = 0;
+  auto fetch = [&](int cp) {
+    f_rl = f_el = f_rho = f_u = f_v = f_w = R(0);
+    f_vx = f_vy = f_vz = 0.0;
+    if (ccol && cp >= 0 && cp < m.nz) {
+      const int64_t q = cidx(m, gi, gj, cp);
+      f_rl = a.geo.rl[q];
+      f_el = a.geo.el[q];
+      f_vx = a.geo.dvx[q];
+      f_vy = a.geo.dvy[q];
+      f_vz = a.geo.dvz[q];
+      f_rho = a.cur.rho[q];
+    }
+    if (ncol && cp >= 0 && cp <= m.nz) {
+      const int64_t n = nidx(m, gi, gj, cp);
+      f_u = a.up[n];
+      f_v = a.vp[n];
+      f_w = a.wp[n];
+    }
+  };
+  // the u' ring starts empty (node planes below Z0-2 only feed non-owned results)
+  for (int q = threadIdx.x; q < 3 * 3 * CH * CW; q += NTH) (&UPR[0][0][0][0])[q] = R(0);
+  fetch(Z0 - 2);
+  __syncthreads();
+
+  for (int c = Z0 - 3; c <= Z1; c++) {  // c >= -3
+    const int c1 = c + 1;
+    const int rA = (c + 5) % 3, rB = (c + 6) % 3, rC = (c + 7) % 3;  // ring rows of c-1, c, c+1
+    // ---- P1 --------------------------------------------------------------------------
+    const R rl_n = f_rl, el_n = f_el, rho_n = f_rho;
+    const double dvz_n = f_vz;
+    RS(RL)[cj][ci] = rl_n;
+    RS(EL)[cj][ci] = el_n;
+    sVX[cj][ci] = f_vx;
+    sVY[cj][ci] = f_vy;
+    UPR[rC][0][cj][ci] = f_u;  // node plane c+1 (slot last read as plane c-2)
+    UPR[rC][1][cj][ci] = f_v;
+    UPR[rC][2][cj][ci] = f_w;
+    fetch(c + 2);
+    __syncthreads();
+    const R uA = UPR[rA][0][cj][ci], vA = UPR[rA][1][cj][ci], wA = UPR[rA][2][cj][ci];
+    const R uB = UPR[rB][0][cj][ci], vB = UPR[rB][1][cj][ci], wB = UPR[rB][2][cj][ci];
+    const R uC = UPR[rC][0][cj][ci], vC = UPR[rC][1][cj][ci], wC = UPR[rC][2][cj][ci];
+    // ---- P2 --------------------------------------------------------------------------
+    R muz_n = 0, epz_n = 0;
+    {
+      const bool pl = c1 >= 0 && c1 < m.nz;
+      R mx = 0, ex = 0, my = 0, ey = 0;
+      if (pl && ci >= 1 && gi >= 1 && gi <= m.nx - 1 && gj >= 0 && gj < m.ny) {
+        const R dv = R(sVX[cj][ci]);
+        const int dn = sVX[cj][ci] > 0.0 ? ci - 1 : ci;
+        mx = RS(RL)[cj][dn] * dv;
+        ex = mx * RS(EL)[cj][dn];
+      }
+      if (pl && cj >= 1 && gj >= 1 && gj <= m.ny - 1 && gi >= 0 && gi < m.nx) {
+        const R dv = R(sVY[cj][ci]);
+        const int dn = sVY[cj][ci] > 0.0 ? cj - 1 : cj;
+        my = RS(RL)[dn][ci] * dv;
+        ey = my * RS(EL)[dn][ci];
+      }
+      if (ccol && c1 >= 1 && c1 <= m.nz - 1) {  // z face between cells c and c+1
+        const bool lower = dvz_n > 0.0;
+        muz_n = (lower ? rl_c : rl_n) * R(dvz_n);
+        epz_n = muz_n * (lower ? el_c : el_n);
+      }
+      RS(MX)[cj][ci] = mx;
+      RS(EX)[cj][ci] = ex;
+      RS(MY)[cj][ci] = my;
+      RS(EY)[cj][ci] = ey;
+    }
+    __syncthreads();
+    // ---- P3 --------------------------------------------------------------------------
+    R ep_c = 0;
+    {
+      R nm = 0, ne = 0, sx = 0, sy = 0, M = 0, mo = 0, sz = 0;
+      if (r1 && ccol && c1 >= 0 && c1 < m.nz) {
+        nm = (RS(MX)[cj][ci + 1] - RS(MX)[cj][ci]) + (RS(MY)[cj + 1][ci] - RS(MY)[cj][ci]);
+        ne = (RS(EX)[cj][ci + 1] - RS(EX)[cj][ci]) + (RS(EY)[cj + 1][ci] - RS(EY)[cj][ci]);
+        sx = RS(MX)[cj][ci] + RS(MX)[cj][ci + 1];
+        sy = RS(MY)[cj][ci] + RS(MY)[cj + 1][ci];
+      }
+      if (r1 && ccol && c >= 0 && c < m.nz) {
+        const R netm = nxm_c + (muz_n - muz_c);
+        const R nete = nxe_c + (epz_n - epz_c);
+        mo = rho_c * V0;
+        M = mo - netm;
+        const R rn = rho_c - netm / V0;
+        const bool mine = own_cell && c >= Z0 && c < Z1;
+        if (!(M > R(0)) || !(rn > R(0)) || !isfinite(rn)) {
+          if (mine) bad = true;
+        } else {
+          ep_c = el_c + (el_c * netm - nete) / M;
+        }
+        if (mine) a.nxt.rho[cidx(m, gi, gj, c)] = rn;
+        sz = muz_c + muz_n;
+      }
+      RS(SX)[cj][ci] = sx;  // slots 0..3 (RL..VY) are dead since P2
+      RS(SY)[cj][ci] = sy;
+      RS(MM)[cj][ci] = M;
+      RS(MO)[cj][ci] = mo;
+      RS(SZ)[cj][ci] = sz;
+      nxm_c = nm;
+      nxe_c = ne;
+    }
+    // plane c+1 becomes plane c
+    rho_c = rho_n;
+    rl_c = rl_n;
+    el_c = el_n;
+    muz_c = muz_n;
+    epz_c = epz_n;
+    __syncthreads();
+    // ---- P4 --------------------------------------------------------------------------
+    R phz = 0, mp = 0, mn = 0;
+    {
+      R qx = 0, qy = 0, pm = 0, pr = 0;
+      if (r1) {
+        const R(*SXs)[CW] = RS(SX);
+        const R(*SYs)[CW] = RS(SY);
+        const R(*SZs)[CW] = RS(SZ);
+        const R(*MMs)[CW] = RS(MM);
+        const R(*MOs)[CW] = RS(MO);
+        qx = SXs[cj - 1][ci] + SXs[cj][ci];  // cells (i, j-1), (i, j) of plane c+1
+        qy = SYs[cj][ci - 1] + SYs[cj][ci];
+        phz = R(0.125) * (((SZs[cj - 1][ci - 1] + SZs[cj - 1][ci]) + SZs[cj][ci - 1]) + SZs[cj][ci]);
+        pm = ((MMs[cj - 1][ci - 1] + MMs[cj - 1][ci]) + MMs[cj][ci - 1]) + MMs[cj][ci];
+        pr = ((MOs[cj - 1][ci - 1] + MOs[cj - 1][ci]) + MOs[cj][ci - 1]) + MOs[cj][ci];
+        mn = R(0.125) * (pm_c1 + pm);
+        mp = R(0.125) * (pr_c1 + pr);
+      }
+      RS(PHX)[cj][ci] = phx_c;  // dual fluxes of node plane c (slots dead since P3)
+      RS(PHY)[cj][ci] = phy_c;
+      phx_c = R(0.125) * (qx_c + qx);  // node plane c+1
+      phy_c = R(0.125) * (qy_c + qy);
+      qx_c = qx;
+      qy_c = qy;
+      pm_c1 = pm;
+      pr_c1 = pr;
+    }
+    __syncthreads();
+    // ---- P5: node plane c --------------------------------------------------------------
+    {
+      R un = 0, vn = 0, wn = 0, sp = 0, dk = 0;
+      if (r2 && ncol && c >= 0 && c <= m.nz) {
+        const int64_t n = nidx(m, gi, gj, c);
+        R P0 = mp * uB, P1 = mp * vB, P2 = mp * wB;
+        R K = R(0.5) * mp * (uB * uB + vB * vB + wB * wB);
+        auto flow = [&](R phi, R ud, R vd, R wd, R sgn) {
+          P0 += sgn * (phi * ud);
+          P1 += sgn * (phi * vd);
+          P2 += sgn * (phi * wd);
+          K += sgn * (phi * R(0.5) * (ud * ud + vd * vd + wd * wd));
+        };
+        const R(*U)[CW] = UPR[rB][0];
+        const R(*V)[CW] = UPR[rB][1];
+        const R(*W)[CW] = UPR[rB][2];
+        const R(*PX)[CW] = RS(PHX);
+        const R(*PY)[CW] = RS(PHY);
+        if (gi + 1 <= m.nx) {
+          const R phi = PX[cj][ci];
+          if (phi > R(0)) flow(phi, uB, vB, wB, R(-1));
+          else flow(phi, U[cj][ci + 1], V[cj][ci + 1], W[cj][ci + 1], R(-1));
+        }
+        if (gi - 1 >= 0) {
+          const R phi = PX[cj][ci - 1];
+          if (phi > R(0)) flow(phi, U[cj][ci - 1], V[cj][ci - 1], W[cj][ci - 1], R(1));
+          else flow(phi, uB, vB, wB, R(1));
+        }
+        if (gj + 1 <= m.ny) {
+          const R phi = PY[cj][ci];
+          if (phi > R(0)) flow(phi, uB, vB, wB, R(-1));
+          else flow(phi, U[cj + 1][ci], V[cj + 1][ci], W[cj + 1][ci], R(-1));
+        }
+        if (gj - 1 >= 0) {
+          const R phi = PY[cj - 1][ci];
+          if (phi > R(0)) flow(phi, U[cj - 1][ci], V[cj - 1][ci], W[cj - 1][ci], R(1));
+          else flow(phi, uB, vB, wB, R(1));
+        }
+        if (c + 1 <= m.nz) {
+          const R phi = phz;
+          if (phi > R(0)) flow(phi, uB, vB, wB, R(-1));
+          else flow(phi, uC, vC, wC, R(-1));
+        }
+        if (c - 1 >= 0) {
+          const R phi = phz_c1;
+          if (phi > R(0)) flow(phi, uA, vA, wA, R(1));
+          else flow(phi, uB, vB, wB, R(1));
+        }
+        const bool mine = own_node && c >= Z0 && c < NZ1;
+        if (!(mn > R(0))) {
+          if (mine) bad = true;
+        } else {
+          un = P0 / mn;
+          vn = P1 / mn;
+          wn = P2 / mn;
+          if (gi == 0 || gi == m.nx) un = R(0);
+          if (gj == 0 || gj == m.ny) vn = R(0);
+          if (c == 0 || c == m.nz) wn = R(0);
+          dk = (K - R(0.5) * mn * (un * un + vn * vn + wn * wn)) / mn;
+          sp = sqrt(un * un + vn * vn + wn * wn);
+        }
+        if (mine) {
+          a.nxt.u[n] = un;
+          a.nxt.v[n] = vn;
+          a.nxt.w[n] = wn;
+        }
+      }
+      RS(UN)[cj][ci] = un;
+      RS(UN + 1)[cj][ci] = vn;
+      RS(UN + 2)[cj][ci] = wn;
+      RS(SP)[cj][ci] = sp;
+      RS(DK)[cj][ci] = dk;
+      phz_c1 = phz;
+    }
+    __syncthreads();
+    // ---- P6: cell plane c-1 ------------------------------------------------------------
+    {
+      R dks = 0, sm = 0, xn = 0, yn = 0, zn = 0;
+      if (r2 && ci <= CW - 3 && cj <= CH - 3) {
+        const R(*U)[CW] = RS(UN);
+        const R(*V)[CW] = RS(UN + 1);
+        const R(*W)[CW] = RS(UN + 2);
+        const R(*S)[CW] = RS(SP);
+        const R(*Q)[CW] = RS(DK);
+        dks = ((Q[cj][ci] + Q[cj][ci + 1]) + Q[cj + 1][ci]) + Q[cj + 1][ci + 1];
+        sm = fmax(fmax(S[cj][ci], S[cj][ci + 1]), fmax(S[cj + 1][ci], S[cj + 1][ci + 1]));
+        xn = (U[cj][ci + 1] - U[cj][ci]) + (U[cj + 1][ci + 1] - U[cj + 1][ci]);
+        yn = (V[cj + 1][ci] - V[cj][ci]) + (V[cj + 1][ci + 1] - V[cj][ci + 1]);
+        zn = ((W[cj][ci] + W[cj][ci + 1]) + W[cj + 1][ci]) + W[cj + 1][ci + 1];
+        const int cm = c - 1;
+        if (own_cell && cm >= Z0 && cm < Z1) {
+          const R en = ep_c1 + R(0.125) * (dks1 + dks);
+          a.nxt.e[cidx(m, gi, gj, cm)] = en;
+          const R D = ((ax * (xn1 + xn) + ay * (yn1 + yn)) + az * (zn - zn1)) / V0;
+          const R sa = signal_from(m, D, en, fmax(sm1, sm));
+          if (!(en >= R(0)) || !isfinite(en) || !isfinite(sa))
+            bad = true;
+          else
+            amax = fmax(amax, (double)sa);
+        }
+      }
+      dks1 = dks;
+      sm1 = sm;
+      xn1 = xn;
+      yn1 = yn;
+      zn1 = zn;
+      ep_c1 = ep_c;
+    }
+    __syncthreads();
+  }
+  *amax_out = amax;
+  *bad_out = bad;
+}
+
+// No-op step of a tile: carry the owned part of the state into the other buffer.
+template <typename R, int CH>
+__device__ void copy_tile(const RunArgs<R> &a, int b) {
+  constexpr int CW = 32, TX = CW - 4, TY = CH - 4;
+  const Mesh &m = a.m;
+  int tx, ty, seg;
+  tile_of(a.gb, b, tx, ty, seg);
+  const int ci = threadIdx.x % CW, cj = threadIdx.x / CW;
+  const int gi = tx * TX + ci - 2, gj = ty * TY + cj - 2;
+  const int Z0 = seg * a.gb.seglen;
+  const bool lastseg = seg == a.gb.nseg - 1;
+  const int Z1 = lastseg ? m.nz : Z0 + a.gb.seglen;
+  const int NZ1 = lastseg ? m.nz + 1 : Z1;
+  const bool own_cell = ci >= 2 && cj >= 2 && ci < 2 + TX && cj < 2 + TY && gi < m.nx && gj < m.ny;
+  const bool own_node = ci >= 2 && cj >= 2 && gi <= m.nx && gj <= m.ny && (ci < 2 + TX || gi == m.nx) &&
+                        (cj < 2 + TY || gj == m.ny);
+  for (int c = Z0; c < Z1; c++)
+    if (own_cell) {
+      const int64_t q = cidx(m, gi, gj, c);
+      a.nxt.rho[q] = a.cur.rho[q];
+      a.nxt.e[q] = a.cur.e[q];
+    }
+  for (int n = Z0; n < NZ1; n++)
+    if (own_node) {
+      const int64_t q = nidx(m, gi, gj, n);
+      a.nxt.u[q] = a.cur.u[q];
+      a.nxt.v[q] = a.cur.v[q];
+      a.nxt.w[q] = a.cur.w[q];
+    }
+}
+
+}  // namespace sale

@@ -16,7 +16,8 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libsale.so")
+# SALE_LIB may name another build of the same library (e.g. a tuning variant)
+LIB_PATH = os.environ.get("SALE_LIB") or os.path.join(HERE, "libsale.so")
 
 # ---- constants (include/sale.h) ----------------------------------------------
 SALE_OK, SALE_DONE = 0, 1
