@@ -152,6 +152,49 @@ int sale_status(sale_ctx *ctx, int32_t *status_flags);
 /* Free the context's host memory (the workspace stays the caller's). */
 void sale_destroy(sale_ctx *ctx);
 
+/* ---- pool: many independent runs, advanced together ------------------------
+ * Batched and served runs: independent runs of different mesh sizes share one
+ * caller-owned device arena and are advanced by one persistent kernel launch
+ * per sale_pool_advance call. The launch pulls (round, phase, run, tile) work
+ * items from a device queue; a run's phase waits only for that run's previous
+ * phase (per-run counters), so runs of uneven size proceed independently. Each
+ * run has its own time step. A run's results do not depend on which other runs
+ * share the pool. */
+typedef struct sale_pool sale_pool;
+
+/* Create a pool of up to max_runs slots over the device arena
+ * [d_arena, d_arena + arena_bytes) (caller-owned, 256-byte aligned, kept alive
+ * until sale_pool_destroy); arena_bytes is the pool's memory budget. All runs
+ * of a pool share `precision`. */
+int sale_pool_create(int32_t precision, int32_t max_runs, void *d_arena, size_t arena_bytes,
+                     void *hip_stream, sale_pool **out);
+
+/* Admit a run: carve its workspace from the arena, write its initial state
+ * (asynchronous) and return its slot. The run stops after n_steps steps or at
+ * cfg->t_end, whichever comes first. cfg->precision must equal the pool's.
+ * SALE_EBUSY if no slot is free or no free arena range is large enough. */
+int sale_pool_admit(sale_pool *pool, const sale_config *cfg, const sale_problem *prob, int64_t n_steps,
+                    int32_t *slot);
+
+/* Enqueue one persistent launch advancing every unfinished admitted run by up
+ * to max_steps_per_run steps (asynchronous). */
+int sale_pool_advance(sale_pool *pool, int32_t max_steps_per_run);
+
+/* Synchronise the stream and list, in done[0..*n_done), the slots whose run
+ * has finished (n_steps taken, t_end reached, or an error flag raised) and
+ * that were not listed by an earlier poll; at most `cap` are listed. */
+int sale_pool_poll(sale_pool *pool, int32_t *done, int32_t cap, int32_t *n_done);
+
+/* sale_fields for one slot (same mask, destinations and types). */
+int sale_pool_fields(sale_pool *pool, int32_t slot, uint32_t mask, void *const *dst, int dst_on_device,
+                     int as_fp64);
+
+/* Return a slot and its arena range to the pool (synchronises the stream). */
+int sale_pool_release(sale_pool *pool, int32_t slot);
+
+/* Free the pool's host memory (the arena stays the caller's). */
+void sale_pool_destroy(sale_pool *pool);
+
 /* Static description of a return code (SALE_EHIP: the last HIP error of the
  * calling thread). */
 const char *sale_strerror(int code);

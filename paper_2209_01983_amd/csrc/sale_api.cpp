@@ -161,6 +161,84 @@ hipError_t enqueue_step(sale_ctx *x) {
   return e;
 }
 
+// Field export shared by single runs and pool slots (see sale_fields).
+int fields_impl(const Mesh &m, int precision, const Work<double> &w64, const Work<float> &w32, int cur,
+                Ctl *ctl, hipStream_t stream, uint32_t mask, void *const *dst, int dst_on_device,
+                int as_fp64) {
+  if (mask && !dst) return SALE_EINVAL;
+  if (mask & ~((SALE_F_TOTALS << 1) - 1u)) return SALE_EINVAL;
+  const hipMemcpyKind kind = dst_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+  const bool fp64 = precision == SALE_FP64;
+  double *scratch = fp64 ? w64.scratch : w32.scratch;
+#define HIP_TRY_F(expr)                               \
+  do {                                                \
+    hipError_t e_ = (expr);                           \
+    if (e_ != hipSuccess) return hip_fail(e_, #expr); \
+  } while (0)
+  int slot = 0;
+  for (uint32_t bit = 1; bit <= SALE_F_TOTALS; bit <<= 1) {
+    if (!(mask & bit)) continue;
+    void *d = dst[slot++];
+    if (!d) return SALE_EINVAL;
+    int which = -1;
+    switch (bit) {
+      case SALE_F_RHO: which = 0; break;
+      case SALE_F_E: which = 1; break;
+      case SALE_F_P: which = 2; break;
+      case SALE_F_Q: which = 3; break;
+      case SALE_F_U: which = 4; break;
+      case SALE_F_V: which = 5; break;
+      case SALE_F_W: which = 6; break;
+      default: break;
+    }
+    if (which >= 0) {
+      const int64_t n = which >= 4 ? m.nnode : m.ncell;
+      const bool derived = which == 2 || which == 3;
+      if (!derived && (fp64 || !as_fp64)) {  // a stored array, copied as is
+        const void *src;
+        size_t esz;
+        if (fp64) {
+          const sale::State<double> &st = w64.s[cur];
+          const double *arr[7] = {st.rho, st.e, nullptr, nullptr, st.u, st.v, st.w};
+          src = arr[which];
+          esz = sizeof(double);
+        } else {
+          const sale::State<float> &st = w32.s[cur];
+          const float *arr[7] = {st.rho, st.e, nullptr, nullptr, st.u, st.v, st.w};
+          src = arr[which];
+          esz = sizeof(float);
+        }
+        HIP_TRY_F(hipMemcpyAsync(d, src, (size_t)n * esz, kind, stream));
+      } else {  // widened or derived: through the scratch array (always double)
+        HIP_TRY_F(fp64 ? sale::launch_export<double>(m, w64, cur, which, scratch, stream)
+                       : sale::launch_export<float>(m, w32, cur, which, scratch, stream));
+        HIP_TRY_F(hipMemcpyAsync(d, scratch, (size_t)n * sizeof(double), kind, stream));
+        HIP_TRY_F(hipStreamSynchronize(stream));  // the scratch array is reused next
+      }
+    } else if (bit == SALE_F_STATE) {
+      Ctl c;
+      int rc = read_ctl(stream, ctl, &c);
+      if (rc != SALE_OK) return rc;
+      double *o = (double *)d;
+      o[0] = c.t;
+      o[1] = (double)c.step;
+      o[2] = next_dt(c, m);
+      o[3] = (double)c.status;
+    } else if (bit == SALE_F_TOTALS) {
+      HIP_TRY_F(fp64 ? sale::launch_totals<double>(m, ctl, w64, cur, stream)
+                     : sale::launch_totals<float>(m, ctl, w32, cur, stream));
+      Ctl c;
+      int rc = read_ctl(stream, ctl, &c);
+      if (rc != SALE_OK) return rc;
+      ((double *)d)[0] = c.totals[0];
+      ((double *)d)[1] = c.totals[1];
+    }
+  }
+  HIP_TRY_F(hipStreamSynchronize(stream));
+#undef HIP_TRY_F
+  return SALE_OK;
+}
+
 }  // namespace sale_host
 
 using namespace sale_host;
@@ -268,73 +346,9 @@ int sale_status(sale_ctx *x, int32_t *flags) {
 }
 
 int sale_fields(sale_ctx *x, uint32_t mask, void *const *dst, int dst_on_device, int as_fp64) {
-  if (!x || (mask && !dst)) return SALE_EINVAL;
-  if (mask & ~((SALE_F_TOTALS << 1) - 1u)) return SALE_EINVAL;
-  const Mesh &m = x->m;
-  const hipMemcpyKind kind = dst_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
-  const bool fp64 = x->precision == SALE_FP64;
-  double *scratch = fp64 ? x->w64.scratch : x->w32.scratch;
-  int slot = 0;
-  for (uint32_t bit = 1; bit <= SALE_F_TOTALS; bit <<= 1) {
-    if (!(mask & bit)) continue;
-    void *d = dst[slot++];
-    if (!d) return SALE_EINVAL;
-    int which = -1;
-    switch (bit) {
-      case SALE_F_RHO: which = 0; break;
-      case SALE_F_E: which = 1; break;
-      case SALE_F_P: which = 2; break;
-      case SALE_F_Q: which = 3; break;
-      case SALE_F_U: which = 4; break;
-      case SALE_F_V: which = 5; break;
-      case SALE_F_W: which = 6; break;
-      default: break;
-    }
-    if (which >= 0) {
-      const int64_t n = which >= 4 ? m.nnode : m.ncell;
-      const bool derived = which == 2 || which == 3;
-      if (!derived && (fp64 || !as_fp64)) {  // a stored array, copied as is
-        const void *src;
-        size_t esz;
-        if (fp64) {
-          const sale::State<double> &s = x->w64.s[x->cur];
-          const double *arr[7] = {s.rho, s.e, nullptr, nullptr, s.u, s.v, s.w};
-          src = arr[which];
-          esz = sizeof(double);
-        } else {
-          const sale::State<float> &s = x->w32.s[x->cur];
-          const float *arr[7] = {s.rho, s.e, nullptr, nullptr, s.u, s.v, s.w};
-          src = arr[which];
-          esz = sizeof(float);
-        }
-        HIP_TRY(hipMemcpyAsync(d, src, (size_t)n * esz, kind, x->stream));
-      } else {  // widened or derived: through the scratch array (always double)
-        HIP_TRY(fp64 ? sale::launch_export<double>(m, x->w64, x->cur, which, scratch, x->stream)
-                     : sale::launch_export<float>(m, x->w32, x->cur, which, scratch, x->stream));
-        HIP_TRY(hipMemcpyAsync(d, scratch, (size_t)n * sizeof(double), kind, x->stream));
-        HIP_TRY(hipStreamSynchronize(x->stream));  // the scratch array is reused next
-      }
-    } else if (bit == SALE_F_STATE) {
-      Ctl c;
-      int rc = read_ctl(x->stream, x->ctl, &c);
-      if (rc != SALE_OK) return rc;
-      double *o = (double *)d;
-      o[0] = c.t;
-      o[1] = (double)c.step;
-      o[2] = next_dt(c, m);
-      o[3] = (double)c.status;
-    } else if (bit == SALE_F_TOTALS) {
-      HIP_TRY(fp64 ? sale::launch_totals<double>(m, x->ctl, x->w64, x->cur, x->stream)
-                   : sale::launch_totals<float>(m, x->ctl, x->w32, x->cur, x->stream));
-      Ctl c;
-      int rc = read_ctl(x->stream, x->ctl, &c);
-      if (rc != SALE_OK) return rc;
-      ((double *)d)[0] = c.totals[0];
-      ((double *)d)[1] = c.totals[1];
-    }
-  }
-  HIP_TRY(hipStreamSynchronize(x->stream));
-  return SALE_OK;
+  if (!x) return SALE_EINVAL;
+  return fields_impl(x->m, x->precision, x->w64, x->w32, x->cur, x->ctl, x->stream, mask, dst, dst_on_device,
+                     as_fp64);
 }
 
 void sale_destroy(sale_ctx *x) { delete x; }
@@ -352,5 +366,288 @@ const char *sale_strerror(int code) {
     default: return "unknown code";
   }
 }
+
+}  // extern "C"
+
+// =====================================================================================
+// pool
+// =====================================================================================
+#include <vector>
+
+namespace sale_host {
+
+struct PoolSlot {
+  bool used = false;
+  bool reported = false;  // listed by a poll as finished
+  size_t off = 0, bytes = 0;
+  Mesh m;
+  Work<double> w64;
+  Work<float> w32;
+  Ctl *ctl = nullptr;  // in the pool header
+  long long step0 = 0;
+  long long step_target = 0;
+  int nA = 0, nB = 0;
+  sale::PoolRun<double> r64;  // host images of the device slot entry
+  sale::PoolRun<float> r32;
+};
+
+}  // namespace sale_host
+
+struct sale_pool {
+  int precision;
+  int max_runs;
+  char *arena;
+  size_t arena_bytes;
+  hipStream_t stream;
+  size_t hdr_bytes;
+  sale::PoolQueue *d_q;
+  void *d_runs;
+  Ctl *d_ctl;
+  int *d_act, *d_prefA, *d_prefB;
+  std::vector<sale_host::PoolSlot> slots;
+  std::vector<std::pair<size_t, size_t>> free_list;  // (offset, size), sorted, disjoint
+  std::vector<int> h_act, h_prefA, h_prefB;
+  std::vector<Ctl> h_ctl;
+  sale::PoolQueue h_q;
+  int resident;
+};
+
+namespace sale_host {
+
+size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+bool pool_alloc(sale_pool *p, size_t bytes, size_t *off) {
+  for (size_t k = 0; k < p->free_list.size(); k++) {
+    auto &fr = p->free_list[k];
+    if (fr.second >= bytes) {
+      *off = fr.first;
+      fr.first += bytes;
+      fr.second -= bytes;
+      if (fr.second == 0) p->free_list.erase(p->free_list.begin() + k);
+      return true;
+    }
+  }
+  return false;
+}
+
+void pool_free(sale_pool *p, size_t off, size_t bytes) {
+  auto &fl = p->free_list;
+  size_t k = 0;
+  while (k < fl.size() && fl[k].first < off) k++;
+  fl.insert(fl.begin() + k, {off, bytes});
+  if (k + 1 < fl.size() && fl[k].first + fl[k].second == fl[k + 1].first) {  // merge right
+    fl[k].second += fl[k + 1].second;
+    fl.erase(fl.begin() + k + 1);
+  }
+  if (k > 0 && fl[k - 1].first + fl[k - 1].second == fl[k].first) {  // merge left
+    fl[k - 1].second += fl[k].second;
+    fl.erase(fl.begin() + k);
+  }
+}
+
+template <typename R>
+sale::PoolRun<R> pool_image(const PoolSlot &sl, const Work<R> &w) {
+  sale::PoolRun<R> r;
+  r.m = sl.m;
+  r.ctl = sl.ctl;
+  r.s[0] = w.s[0];
+  r.s[1] = w.s[1];
+  r.up = w.up;
+  r.vp = w.vp;
+  r.wp = w.wp;
+  r.geo = w.geo;
+  // one z segment per tile: the pool's parallelism comes from its many runs
+  r.ga = sale::grid_lagrange(sl.m, 1);
+  r.gb = sale::grid_remap(sl.m, 1);
+  r.step0 = sl.step0;
+  r.step_target = sl.step_target;
+  return r;
+}
+
+bool finished(const Ctl &c, long long step_target) {
+  return c.status != 0u || c.t >= c.t_end || c.step >= step_target;
+}
+
+}  // namespace sale_host
+
+extern "C" {
+
+int sale_pool_create(int32_t precision, int32_t max_runs, void *d_arena, size_t arena_bytes, void *hip_stream,
+                     sale_pool **out) {
+  if (!out) return SALE_EINVAL;
+  *out = nullptr;
+  if ((precision != SALE_FP64 && precision != SALE_MIXED32) || max_runs < 1 || max_runs > (1 << 20))
+    return SALE_EINVAL;
+  if (!d_arena || ((uintptr_t)d_arena & 255u)) return SALE_EINVAL;
+  const size_t run_sz = precision == SALE_FP64 ? sizeof(sale::PoolRun<double>) : sizeof(sale::PoolRun<float>);
+  size_t hdr = a256(sizeof(sale::PoolQueue)) + a256((size_t)max_runs * run_sz) + a256((size_t)max_runs * sizeof(Ctl)) +
+               3 * a256((size_t)(max_runs + 1) * sizeof(int));
+  if (arena_bytes < hdr) return SALE_ENOMEM;
+  sale_pool *p = new (std::nothrow) sale_pool;
+  if (!p) return SALE_ENOMEM;
+  p->precision = precision;
+  p->max_runs = max_runs;
+  p->arena = (char *)d_arena;
+  p->arena_bytes = arena_bytes;
+  p->stream = (hipStream_t)hip_stream;
+  p->hdr_bytes = hdr;
+  char *q = p->arena;
+  p->d_q = (sale::PoolQueue *)q;
+  q += a256(sizeof(sale::PoolQueue));
+  p->d_runs = q;
+  q += a256((size_t)max_runs * run_sz);
+  p->d_ctl = (Ctl *)q;
+  q += a256((size_t)max_runs * sizeof(Ctl));
+  p->d_act = (int *)q;
+  q += a256((size_t)(max_runs + 1) * sizeof(int));
+  p->d_prefA = (int *)q;
+  q += a256((size_t)(max_runs + 1) * sizeof(int));
+  p->d_prefB = (int *)q;
+  p->slots.resize(max_runs);
+  p->free_list.push_back({hdr, arena_bytes - hdr});
+  p->h_ctl.resize(max_runs);
+  p->resident = precision == SALE_FP64 ? sale::pool_resident_blocks<double>() : sale::pool_resident_blocks<float>();
+  *out = p;
+  return SALE_OK;
+}
+
+int sale_pool_admit(sale_pool *p, const sale_config *cfg, const sale_problem *prob, int64_t n_steps,
+                    int32_t *slot) {
+  if (!p || !slot || n_steps < 0) return SALE_EINVAL;
+  int rc = validate_config(cfg);
+  if (rc != SALE_OK) return rc;
+  if (cfg->precision != p->precision) return SALE_EINVAL;
+  const Mesh m = make_mesh(cfg);
+  if ((rc = validate_problem(prob, m)) != SALE_OK) return rc;
+  int s = -1;
+  for (int k = 0; k < p->max_runs; k++)
+    if (!p->slots[k].used) {
+      s = k;
+      break;
+    }
+  if (s < 0) return SALE_EBUSY;
+  const size_t bytes = a256(ws_bytes_for(m, p->precision));
+  size_t off;
+  if (!pool_alloc(p, bytes, &off)) return SALE_EBUSY;
+  PoolSlot &sl = p->slots[s];
+  sl.off = off;
+  sl.bytes = bytes;
+  sl.m = m;
+  sl.ctl = p->d_ctl + s;
+  sl.step0 = prob->step0;
+  sl.step_target = prob->step0 + n_steps;
+  sl.reported = false;
+  Ctl *unused;
+  hipError_t e;
+  if (p->precision == SALE_FP64) {
+    sale::layout<double>(m, p->arena + off, &unused, &sl.w64);
+    e = init_problem<double>(m, sl.ctl, sl.w64, prob, cfg->t_end, p->stream);
+    sl.r64 = pool_image<double>(sl, sl.w64);
+    sl.nA = sl.r64.ga.blocks();
+    sl.nB = sl.r64.gb.blocks();
+    if (e == hipSuccess)
+      e = hipMemcpyAsync((sale::PoolRun<double> *)p->d_runs + s, &sl.r64, sizeof(sl.r64), hipMemcpyHostToDevice,
+                         p->stream);
+  } else {
+    sale::layout<float>(m, p->arena + off, &unused, &sl.w32);
+    e = init_problem<float>(m, sl.ctl, sl.w32, prob, cfg->t_end, p->stream);
+    sl.r32 = pool_image<float>(sl, sl.w32);
+    sl.nA = sl.r32.ga.blocks();
+    sl.nB = sl.r32.gb.blocks();
+    if (e == hipSuccess)
+      e = hipMemcpyAsync((sale::PoolRun<float> *)p->d_runs + s, &sl.r32, sizeof(sl.r32), hipMemcpyHostToDevice,
+                         p->stream);
+  }
+  // the host images are read by the copy above: keep them unchanged until it ran
+  if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+  if (e != hipSuccess) {
+    pool_free(p, off, bytes);
+    return hip_fail(e, "sale_pool_admit");
+  }
+  sl.used = true;
+  *slot = s;
+  return SALE_OK;
+}
+
+int sale_pool_advance(sale_pool *p, int32_t max_steps_per_run) {
+  if (!p || max_steps_per_run < 0) return SALE_EINVAL;
+  if (max_steps_per_run == 0) return SALE_OK;
+  // the host tables of the previous advance may still be in a copy: wait
+  hipError_t e = hipStreamSynchronize(p->stream);
+  if (e != hipSuccess) return hip_fail(e, "sale_pool_advance");
+  p->h_act.clear();
+  p->h_prefA.assign(1, 0);
+  p->h_prefB.assign(1, 0);
+  for (int k = 0; k < p->max_runs; k++) {
+    const PoolSlot &sl = p->slots[k];
+    if (!sl.used || sl.reported) continue;
+    p->h_act.push_back(k);
+    p->h_prefA.push_back(p->h_prefA.back() + sl.nA);
+    p->h_prefB.push_back(p->h_prefB.back() + sl.nB);
+  }
+  const int nact = (int)p->h_act.size();
+  if (nact == 0) return SALE_OK;
+  p->h_q.head = 0;
+  p->h_q.nact = nact;
+  p->h_q.rounds = max_steps_per_run;
+  p->h_q.totA = p->h_prefA.back();
+  p->h_q.totB = p->h_prefB.back();
+  p->h_q.timeouts = 0;
+  p->h_q.abort = 0;
+  const unsigned long long items =
+      (unsigned long long)(p->h_q.totA + p->h_q.totB) * (unsigned long long)max_steps_per_run;
+  const int blocks = (int)std::min<unsigned long long>((unsigned long long)p->resident, items);
+  HIP_TRY(hipMemcpyAsync(p->d_act, p->h_act.data(), nact * sizeof(int), hipMemcpyHostToDevice, p->stream));
+  HIP_TRY(hipMemcpyAsync(p->d_prefA, p->h_prefA.data(), (nact + 1) * sizeof(int), hipMemcpyHostToDevice, p->stream));
+  HIP_TRY(hipMemcpyAsync(p->d_prefB, p->h_prefB.data(), (nact + 1) * sizeof(int), hipMemcpyHostToDevice, p->stream));
+  HIP_TRY(hipMemcpyAsync(p->d_q, &p->h_q, sizeof(p->h_q), hipMemcpyHostToDevice, p->stream));
+  if (p->precision == SALE_FP64)
+    HIP_TRY(sale::launch_pool_advance<double>((sale::PoolRun<double> *)p->d_runs, p->d_act, p->d_prefA, p->d_prefB,
+                                              p->d_q, nact, blocks, p->stream));
+  else
+    HIP_TRY(sale::launch_pool_advance<float>((sale::PoolRun<float> *)p->d_runs, p->d_act, p->d_prefA, p->d_prefB,
+                                             p->d_q, nact, blocks, p->stream));
+  return SALE_OK;
+}
+
+int sale_pool_poll(sale_pool *p, int32_t *done, int32_t cap, int32_t *n_done) {
+  if (!p || !n_done || cap < 0 || (cap > 0 && !done)) return SALE_EINVAL;
+  *n_done = 0;
+  HIP_TRY(hipMemcpyAsync(p->h_ctl.data(), p->d_ctl, p->max_runs * sizeof(Ctl), hipMemcpyDeviceToHost, p->stream));
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  for (int k = 0; k < p->max_runs && *n_done < cap; k++) {
+    PoolSlot &sl = p->slots[k];
+    if (!sl.used || sl.reported) continue;
+    if (finished(p->h_ctl[k], sl.step_target)) {
+      sl.reported = true;
+      done[(*n_done)++] = k;
+    }
+  }
+  return SALE_OK;
+}
+
+int sale_pool_fields(sale_pool *p, int32_t slot, uint32_t mask, void *const *dst, int dst_on_device,
+                     int as_fp64) {
+  if (!p || slot < 0 || slot >= p->max_runs || !p->slots[slot].used) return SALE_EINVAL;
+  PoolSlot &sl = p->slots[slot];
+  Ctl c;
+  int rc = read_ctl(p->stream, sl.ctl, &c);
+  if (rc != SALE_OK) return rc;
+  const int cur = (int)((c.step - sl.step0) & 1);
+  return fields_impl(sl.m, p->precision, sl.w64, sl.w32, cur, sl.ctl, p->stream, mask, dst, dst_on_device,
+                     as_fp64);
+}
+
+int sale_pool_release(sale_pool *p, int32_t slot) {
+  if (!p || slot < 0 || slot >= p->max_runs || !p->slots[slot].used) return SALE_EINVAL;
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  PoolSlot &sl = p->slots[slot];
+  pool_free(p, sl.off, sl.bytes);
+  sl.used = false;
+  sl.reported = false;
+  return SALE_OK;
+}
+
+void sale_pool_destroy(sale_pool *p) { delete p; }
 
 }  // extern "C"

@@ -128,4 +128,36 @@ RunArgs<R> run_args(const Mesh &m, Ctl *ctl, const Work<R> &w, int cur, int targ
 template <typename R>
 hipError_t launch_export(const Mesh &m, const Work<R> &w, int cur, int which, double *out, hipStream_t s);
 
+// Device-side description of one pool slot.
+template <typename R>
+struct PoolRun {
+  Mesh m;
+  Ctl *ctl;
+  State<R> s[2];
+  R *up, *vp, *wp;
+  Geo<R> geo;
+  Grid2 ga, gb;
+  long long step0;  // step count at admission: state buffer = (step - step0) & 1
+  long long step_target;
+};
+
+// Queue header and the active-run tables of one advance.
+struct PoolQueue {
+  unsigned long long head;  // next item to hand out
+  int nact;                 // active runs in this advance
+  int rounds;               // steps per run in this advance
+  int totA, totB;           // Lagrange / remap tiles over all active runs
+  unsigned int timeouts;    // waits that hit the time cap
+  unsigned int abort;       // set by a timed-out wait: later waits give up at once
+};
+
+// Persistent multi-run advance: prepare (queue head, per-run counters, first
+// dt) and the persistent kernel over `blocks` blocks; tables on the device.
+template <typename R>
+hipError_t launch_pool_advance(PoolRun<R> *runs, const int *act, const int *prefA, const int *prefB,
+                               PoolQueue *qh, int nact, int blocks, hipStream_t s);
+// Blocks of the persistent kernel that fit on the device at once.
+template <typename R>
+int pool_resident_blocks();
+
 }  // namespace sale

@@ -65,6 +65,31 @@ __device__ __forceinline__ R signal_from(const Mesh &m, R D, R e, R smax) {
   return cs + smax + R(4) * R(m.cq) * R(m.h) * fmax(-D, R(0));
 }
 
+// O3 at the start of a step: dt from the largest signal speed of the current
+// state (CFL h / a_max, clipped to land on t_end) and the done decision (error
+// flag raised, t_end reached, or the run's step target reached). Run by one
+// thread; every kernel of the step then reads ctl->dt and ctl->done.
+__device__ __forceinline__ void begin_step(const Mesh &m, Ctl *ctl, long long step_target) {
+  if (ctl->status != 0u || ctl->t >= ctl->t_end || ctl->step >= step_target) {
+    ctl->done = 1u;
+    return;
+  }
+  const double amax = __longlong_as_double((long long)ctl->amax_bits);
+  const double rem = ctl->t_end - ctl->t;
+  double dt = amax > 0.0 ? m.cfl * m.h / amax : rem;
+  if (dt > rem) dt = rem;
+  if (!(dt > 0.0) || !isfinite(dt)) {
+    ctl->status |= SALE_FLAG_NUMERIC;
+    ctl->done = 1u;
+    return;
+  }
+  ctl->dt = dt;
+  ctl->done = 0u;
+  ctl->t = ctl->t + dt;
+  ctl->step += 1;
+  ctl->amax_bits = 0ull;
+}
+
 __device__ __forceinline__ void tile_of(const Grid2 &g, int b, int &tx, int &ty, int &seg) {
   tx = b % g.tx;
   const int r = b / g.tx;

@@ -38,6 +38,8 @@ NODE_FIELDS = ("u", "v", "w")
 # functions the header declares (checked by the tests against include/sale.h)
 EXPORTS = ("sale_workspace_bytes", "sale_init", "sale_step", "sale_run", "sale_fields",
            "sale_status", "sale_destroy", "sale_strerror")
+POOL_EXPORTS = ("sale_pool_create", "sale_pool_admit", "sale_pool_advance", "sale_pool_poll",
+                "sale_pool_fields", "sale_pool_release", "sale_pool_destroy")
 
 
 class sale_config(C.Structure):
@@ -90,6 +92,22 @@ def lib():
         L.sale_destroy.restype = None
         L.sale_strerror.argtypes = [C.c_int]
         L.sale_strerror.restype = C.c_char_p
+        L.sale_pool_create.argtypes = [C.c_int32, C.c_int32, C.c_void_p, C.c_size_t, C.c_void_p,
+                                       C.POINTER(C.c_void_p)]
+        L.sale_pool_create.restype = C.c_int
+        L.sale_pool_admit.argtypes = [C.c_void_p, cp, pp, C.c_int64, C.POINTER(C.c_int32)]
+        L.sale_pool_admit.restype = C.c_int
+        L.sale_pool_advance.argtypes = [C.c_void_p, C.c_int32]
+        L.sale_pool_advance.restype = C.c_int
+        L.sale_pool_poll.argtypes = [C.c_void_p, C.POINTER(C.c_int32), C.c_int32, C.POINTER(C.c_int32)]
+        L.sale_pool_poll.restype = C.c_int
+        L.sale_pool_fields.argtypes = [C.c_void_p, C.c_int32, C.c_uint32, C.POINTER(C.c_void_p), C.c_int,
+                                       C.c_int]
+        L.sale_pool_fields.restype = C.c_int
+        L.sale_pool_release.argtypes = [C.c_void_p, C.c_int32]
+        L.sale_pool_release.restype = C.c_int
+        L.sale_pool_destroy.argtypes = [C.c_void_p]
+        L.sale_pool_destroy.restype = None
         _lib = L
     return _lib
 
@@ -139,6 +157,46 @@ def sale_strerror(code: int) -> str:
     return lib().sale_strerror(code).decode()
 
 
+def sale_pool_create(precision: int, max_runs: int, d_arena: int, arena_bytes: int, stream: int):
+    """Returns (code, pool handle or None)."""
+    pool = C.c_void_p(None)
+    rc = lib().sale_pool_create(precision, max_runs, C.c_void_p(d_arena), arena_bytes, C.c_void_p(stream),
+                                C.byref(pool))
+    return rc, (pool if rc == SALE_OK else None)
+
+
+def sale_pool_admit(pool, cfg: sale_config, prob: sale_problem, n_steps: int):
+    """Returns (code, slot)."""
+    slot = C.c_int32(-1)
+    rc = lib().sale_pool_admit(pool, C.byref(cfg), C.byref(prob), n_steps, C.byref(slot))
+    return rc, slot.value
+
+
+def sale_pool_advance(pool, max_steps_per_run: int) -> int:
+    return lib().sale_pool_advance(pool, max_steps_per_run)
+
+
+def sale_pool_poll(pool, cap: int):
+    """Returns (code, list of finished slots)."""
+    buf = (C.c_int32 * max(1, cap))()
+    n = C.c_int32(0)
+    rc = lib().sale_pool_poll(pool, buf, cap, C.byref(n))
+    return rc, list(buf[: n.value])
+
+
+def sale_pool_fields(pool, slot: int, mask: int, dst_ptrs, dst_on_device: int, as_fp64: int) -> int:
+    arr = (C.c_void_p * max(1, len(dst_ptrs)))(*[C.c_void_p(p) for p in dst_ptrs])
+    return lib().sale_pool_fields(pool, slot, mask, arr, dst_on_device, as_fp64)
+
+
+def sale_pool_release(pool, slot: int) -> int:
+    return lib().sale_pool_release(pool, slot)
+
+
+def sale_pool_destroy(pool) -> None:
+    lib().sale_pool_destroy(pool)
+
+
 # ---- helpers ------------------------------------------------------------------------
 def make_config(nx, ny, nz, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), gamma=1.4, cfl=0.5,
                 c_quad=1.0, c_lin=0.5, t_end=1.0, precision=SALE_FP64) -> sale_config:
@@ -182,6 +240,22 @@ def user_problem(rho, e, u, v, w, t0=0.0, step0=0):
         p.user_on_device = 1
     p.rho, p.e, p.u, p.v, p.w = ptrs
     return p, arrs
+
+
+def _field_buffers(torch, device, names, cell_shape, node_shape, on_device):
+    names = sorted(names, key=lambda n: FIELD_BITS[n])
+    out, ptrs, mask = {}, [], 0
+    for n in names:
+        shape = cell_shape if n in CELL_FIELDS else node_shape
+        if on_device:
+            a = torch.empty(shape, dtype=torch.float64, device=device)
+            ptrs.append(a.data_ptr())
+        else:
+            a = np.empty(shape, dtype=np.float64)
+            ptrs.append(a.ctypes.data)
+        out[n] = a
+        mask |= FIELD_BITS[n]
+    return out, ptrs, mask
 
 
 class SaleRun:
@@ -229,19 +303,8 @@ class SaleRun:
     def fields(self, names=("rho", "e", "u", "v", "w"), on_device=False):
         """Dict of float64 arrays in the logical layout (numpy, or torch CUDA
         tensors with on_device=True)."""
-        torch = self.torch
-        names = sorted(names, key=lambda n: FIELD_BITS[n])
-        out, ptrs, mask = {}, [], 0
-        for n in names:
-            shape = self.cell_shape if n in CELL_FIELDS else self.node_shape
-            if on_device:
-                a = torch.empty(shape, dtype=torch.float64, device=self.device)
-                ptrs.append(a.data_ptr())
-            else:
-                a = np.empty(shape, dtype=np.float64)
-                ptrs.append(a.ctypes.data)
-            out[n] = a
-            mask |= FIELD_BITS[n]
+        out, ptrs, mask = _field_buffers(self.torch, self.device, names, self.cell_shape, self.node_shape,
+                                         on_device)
         rc = sale_fields(self.ctx, mask, ptrs, int(on_device), 1)
         if rc != SALE_OK:
             raise SaleError(rc, "sale_fields")
@@ -262,3 +325,76 @@ class SaleRun:
         if rc != SALE_OK:
             raise SaleError(rc, "sale_fields")
         return float(o[0]), float(o[1])
+
+
+class Pool:
+    """Many independent runs in one device arena (a torch uint8 tensor of
+    `arena_bytes` on `device`), advanced together by the library's persistent
+    kernel on torch's current stream."""
+
+    def __init__(self, arena_bytes, max_runs=256, precision=SALE_FP64, device="cuda:0"):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device)
+        self.arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device=self.device)
+        self.stream = torch.cuda.current_stream(self.device).cuda_stream
+        rc, self.pool = sale_pool_create(precision, max_runs, self.arena.data_ptr(), int(arena_bytes),
+                                         self.stream)
+        if rc != SALE_OK:
+            raise SaleError(rc, "sale_pool_create")
+        self.max_runs = max_runs
+        self.shapes = {}
+
+    def close(self):
+        if getattr(self, "pool", None):
+            sale_pool_destroy(self.pool)
+            self.pool = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def admit(self, cfg: sale_config, prob: sale_problem, n_steps: int):
+        """Slot of the admitted run, or None when the pool is full (SALE_EBUSY)."""
+        rc, slot = sale_pool_admit(self.pool, cfg, prob, n_steps)
+        if rc == SALE_EBUSY:
+            return None
+        if rc != SALE_OK:
+            raise SaleError(rc, "sale_pool_admit")
+        self.shapes[slot] = ((cfg.nz, cfg.ny, cfg.nx), (cfg.nz + 1, cfg.ny + 1, cfg.nx + 1))
+        return slot
+
+    def advance(self, max_steps_per_run: int):
+        rc = sale_pool_advance(self.pool, max_steps_per_run)
+        if rc != SALE_OK:
+            raise SaleError(rc, "sale_pool_advance")
+
+    def poll(self, cap=None):
+        rc, done = sale_pool_poll(self.pool, self.max_runs if cap is None else cap)
+        if rc != SALE_OK:
+            raise SaleError(rc, "sale_pool_poll")
+        return done
+
+    def fields(self, slot, names=("rho", "e", "u", "v", "w"), on_device=False):
+        cell, node = self.shapes[slot]
+        out, ptrs, mask = _field_buffers(self.torch, self.device, names, cell, node, on_device)
+        rc = sale_pool_fields(self.pool, slot, mask, ptrs, int(on_device), 1)
+        if rc != SALE_OK:
+            raise SaleError(rc, "sale_pool_fields")
+        return out
+
+    def state(self, slot):
+        """(t, steps, next dt, status flags) of one slot."""
+        o = np.zeros(4)
+        rc = sale_pool_fields(self.pool, slot, SALE_F_STATE, [o.ctypes.data], 0, 1)
+        if rc != SALE_OK:
+            raise SaleError(rc, "sale_pool_fields")
+        return float(o[0]), int(o[1]), float(o[2]), int(o[3])
+
+    def release(self, slot):
+        rc = sale_pool_release(self.pool, slot)
+        if rc != SALE_OK:
+            raise SaleError(rc, "sale_pool_release")
+        self.shapes.pop(slot, None)

@@ -26,7 +26,7 @@ def test_library_exports_every_declared_function():
     for name in decl:
         assert hasattr(L, name), name
     assert sorted(sale.EXPORTS) == sorted(n for n in decl if n in sale.EXPORTS)
-    assert set(decl) <= set(sale.EXPORTS) | set(getattr(sale, "POOL_EXPORTS", ()))
+    assert set(decl) == set(sale.EXPORTS) | set(sale.POOL_EXPORTS)
 
 
 def test_struct_layout_matches_header_sizes():
@@ -82,3 +82,20 @@ def test_strerror_covers_every_code():
     for code in (0, 1, -1, -2, -3, -4, -5, -6):
         assert sale.sale_strerror(code) != "unknown code"
     assert sale.sale_strerror(99) == "unknown code"
+
+
+def test_pool_create_rejects_invalid_arguments_before_device_work():
+    big = 1 << 30
+    assert sale.sale_pool_create(7, 4, 256, big, 0)[0] == sale.SALE_EINVAL        # precision
+    assert sale.sale_pool_create(sale.SALE_FP64, 0, 256, big, 0)[0] == sale.SALE_EINVAL  # no slots
+    assert sale.sale_pool_create(sale.SALE_FP64, 4, 0, big, 0)[0] == sale.SALE_EINVAL    # no arena
+    assert sale.sale_pool_create(sale.SALE_FP64, 4, 128, big, 0)[0] == sale.SALE_EINVAL  # misaligned
+    assert sale.sale_pool_create(sale.SALE_FP64, 4, 256, 512, 0)[0] == sale.SALE_ENOMEM  # header only
+    L = sale.lib()
+    out = C.c_int32(0)
+    assert L.sale_pool_admit(None, None, None, 1, C.byref(out)) == sale.SALE_EINVAL
+    assert L.sale_pool_advance(None, 1) == sale.SALE_EINVAL
+    assert L.sale_pool_poll(None, None, 0, C.byref(out)) == sale.SALE_EINVAL
+    assert L.sale_pool_fields(None, 0, 1, None, 0, 1) == sale.SALE_EINVAL
+    assert L.sale_pool_release(None, 0) == sale.SALE_EINVAL
+    L.sale_pool_destroy(None)

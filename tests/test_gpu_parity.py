@@ -16,7 +16,7 @@ from oracle.exact import sedov_radius
 from paper_2209_01983_amd import sale
 from paper_2209_01983_amd.inputs import random_state
 
-from parity import FIELDS, TOL64, assert_parity, errors, grid_of, oracle_state, say
+from parity import FIELDS, TOL64, assert_parity, errors, grid_of, oracle_state, say  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
@@ -287,3 +287,69 @@ def test_error_codes_match_oracle():
         assert np.array_equal(f0[k], f1[k])
     # a later end time continues the run
     assert r.run(t_end=0.1) == sale.SALE_DONE and r.state()[0] == 0.1
+
+
+# ---------------------------------------------------------------------------
+# MIXED32: FP32 bulk arithmetic, FP64 geometry / dt / totals
+# ---------------------------------------------------------------------------
+# Stated error bars (relative to the field's scale, as above): one step from a
+# smooth random state <= 5e-6 per field; the Sod tube to t = 0.2 <= 5e-6 vs the
+# FP64 oracle; mass and energy drift of a Sedov run <= 1e-6 / 1e-5.
+TOL32_STEP = 5e-6
+
+
+def mixed_cfg(*a, **k):
+    return sale.make_config(*a, precision=sale.SALE_MIXED32, **k)
+
+
+def test_mixed32_single_steps_vs_fp64_oracle():
+    n = (37, 29, 23)
+    cfg = mixed_cfg(*n, hi=(1.0, 0.8, 1.3), t_end=100.0)
+    st = random_state(*n, seed=1, smooth=True)
+    r = user_run(cfg, st)
+    s = oracle_state(st)
+    o = orc.Oracle(grid_of(cfg))
+    for step in range(5):
+        assert o.step(s)[0] == orc.OK
+        r.step()
+        err = errors(r.fields(), s)
+        assert max(err.values()) <= TOL32_STEP, (step, err)
+    say("mixed32 5-step errors", err)
+
+
+def test_mixed32_sod_tube_vs_fp64_oracle():
+    cfg = mixed_cfg(64, 4, 4, hi=(1.0, 0.0625, 0.0625), t_end=0.2)
+    r = sale.SaleRun(cfg, sale.sod_problem())
+    assert r.run() == sale.SALE_DONE
+    g = grid_of(cfg)
+    s = orc.sod(g)
+    assert orc.Oracle(g).run(s)[0] == orc.DONE
+    t, steps, _, flags = r.state()
+    assert t == 0.2 and flags == 0 and steps == s.step
+    err = errors(r.fields(), s)
+    say("mixed32 sod errors", err)
+    assert max(err.values()) <= 5e-6
+    # storage type export is float32 and equals the widened export
+    f32 = np.empty((4, 4, 64), dtype=np.float32)
+    assert sale.sale_fields(r.ctx, sale.SALE_F_RHO, [f32.ctypes.data], 0, 0) == sale.SALE_OK
+    assert np.array_equal(f32.astype(np.float64), r.fields(("rho",))["rho"])
+
+
+def test_mixed32_sedov_conservation_and_agreement_with_fp64():
+    out = {}
+    for prec in (sale.SALE_FP64, sale.SALE_MIXED32):
+        cfg = sale.make_config(48, 48, 48, hi=(1.2, 1.2, 1.2), t_end=0.3, precision=prec)
+        r = sale.SaleRun(cfg, sale.sedov_problem())
+        m0, E0 = r.totals()
+        assert r.run() == sale.SALE_DONE
+        m1, E1 = r.totals()
+        out[prec] = (r.fields(), (m1 - m0) / m0, (E1 - E0) / E0, r.state()[1])
+    f64, dm64, de64, n64 = out[sale.SALE_FP64]
+    f32, dm32, de32, n32 = out[sale.SALE_MIXED32]
+    assert abs(dm64) <= 1e-13 and abs(de64) <= 1e-12
+    assert abs(dm32) <= 1e-6 and abs(de32) <= 1e-5
+    assert n32 == n64
+    for k in FIELDS:
+        l1 = np.abs(f32[k] - f64[k]).sum() / np.abs(f64[k]).sum()
+        assert l1 <= 1e-4, (k, l1)
+    say("mixed32 sedov48 drift", dm32, de32)
