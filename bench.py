@@ -1,22 +1,41 @@
 #!/usr/bin/env python3
-"""Benchmark: cell-updates/s of the SALE Lagrange + remap step on one MI355X.
+"""Benchmark of the SALE Lagrange + remap step on one MI355X.
 
-Workload: the Sedov blast on a 320^3 octant mesh of [0,1.2]^3 (rho = 1,
-p = 1e-6, E = 0.125 deposited in the corner cell, gamma 1.4, CFL 0.5),
-FP64, synthetic initial state generated on the device. W warm-up steps, then
-K timed steps between two stream synchronisations; value = cells x K / time.
+Headline (`value`): cell-updates/s of the FP64 step on the Sedov blast,
+320^3 octant mesh of [0,1.2]^3 (rho = 1, p = 1e-6, E = 0.125 in the corner
+cell, gamma 1.4, CFL 0.5), synthetic state generated on the device. W warm-up
+steps, then K timed steps between HIP events on the library's stream;
+value = cells x K / time. The same window in MIXED32 is reported beside it.
 
-Prints one JSON line. `roofline` covers the step's HBM roofline (the step is
-a bandwidth-bound stencil; no MFMA): algorithmic bytes = read and write of
-the state once per step (rho, e per cell; u, v, w per node, FP64). The CPU
-baseline is the FP64 oracle timed on this host's cores on a few steps of the
-same workload.
+Also reported (one JSON line, extra keys):
+  roofline     the step as the unit of the HBM roofline: algorithmic bytes =
+               read + write of the state once per step, 80.45 B/cell at 320^3
+               FP64, over the summed duration of the step's kernels (HIP
+               events around each kernel on the library's stream); per-kernel
+               durations and their compulsory bytes; HBM traffic measured
+               with rocprofv3 counters when the committed counter summary
+               matches the current kernel sources (else null).
+  latency      Sod 64x4x4 to t = 0.2, FP64: full-run latency p50/p99 over
+               repeated runs (init, steps and the status read; launch bound).
+  sedov128     Sedov 128^3 to t = 1.0, FP64: full-run latency and
+               cell-updates/s.
+  batched      256 runs (seeded mix of Sod / Sedov, edges 16..64), MIXED32,
+               200 steps each in ONE persistent launch: aggregate
+               cell-updates/s, makespan, per-run latency p50/p99; the same
+               runs one after another on the plain FP64 path.
+  serving      seeded Poisson trace (50 requests/s, cubic 32^3..192^3,
+               100..500 steps), continuous batching under an HBM budget, in
+               MIXED32 and FP64: throughput and arrival -> result latency.
+  cpu_baseline the FP64 oracle on this host's cores, a few steps of the
+               320^3 workload.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--quick] [--no-cpu]
 """
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -25,55 +44,193 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+KERNEL_SOURCES = ("sale_device.h", "sale_tiles.h", "sale_step.hip", "sale_impl.h")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pmc_traffic_sedov320.md")
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100)
-    ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--n", type=int, default=320, help="cells per axis")
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--n", type=int, default=320, help="cells per axis of the headline workload")
+    ap.add_argument("--quick", action="store_true", help="headline and roofline only")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--cpu-steps", type=int, default=10)
+    ap.add_argument("--serve-requests", type=int, default=1000)
+    ap.add_argument("--serve-budget-gb", type=float, default=64.0)
     return ap.parse_args()
 
 
-def algorithmic_bytes(n):
-    ncell = n ** 3
-    nnode = (n + 1) ** 3
-    return 2 * (2 * ncell + 3 * nnode) * 8  # read + write rho, e, u, v, w (FP64)
+def say(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def gpu_bench(n, steps, warmup, precision=0):
+def pct(xs, q):
+    import numpy as np
+    return float(np.percentile(np.asarray(xs, dtype=float), q))
+
+
+# ---- byte model ------------------------------------------------------------------
+def algorithmic_bytes(n, esz=8):
+    """Read + write of the state once per step: rho, e per cell, u, v, w per node."""
+    return 2 * (2 * n ** 3 + 3 * (n + 1) ** 3) * esz
+
+
+def compulsory_bytes(n, esz=8):
+    """What each step kernel must move given its inputs and outputs (R = esz
+    bytes; swept volumes always FP64): Lagrange+geometry reads rho, e, u, v, w
+    and writes u', v', w', rho^L, e^L and three swept volumes per cell; remap
+    reads rho^L, e^L, the swept volumes, rho and u', v', w' and writes rho, e,
+    u, v, w."""
+    c, p = n ** 3, (n + 1) ** 3
+    lag = c * (2 * esz) + p * (3 * esz) + p * (3 * esz) + c * (2 * esz + 3 * 8)
+    rem = c * (3 * esz + 3 * 8) + p * (3 * esz) + c * (2 * esz) + p * (3 * esz)
+    return {"k_lagrange": lag, "k_remap": rem}
+
+
+def kernel_source_digest():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2209_01983_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per step from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel sources."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None, "no counter summary"
+    text = open(TRAFFIC_FILE).read()
+    m = re.search(r"kernel sources sha256\[:16\]:\s*([0-9a-f]{16})", text)
+    b = re.search(r"traffic bytes per step \(fp64\):\s*([0-9.eE+]+)", text)
+    if not m or not b:
+        return None, "counter summary unreadable"
+    if m.group(1) != kernel_source_digest():
+        return None, "kernels changed since the counters were taken"
+    return float(b.group(1)), "rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated"
+
+
+# ---- workloads -----------------------------------------------------------------
+def headline(n, steps, warmup, precision):
+    """(ms per step from HIP events around `steps` async steps, final t)."""
     import torch
-
     from paper_2209_01983_amd import sale
 
     cfg = sale.make_config(n, n, n, hi=(1.2, 1.2, 1.2), t_end=1.0, precision=precision)
     run = sale.SaleRun(cfg, sale.sedov_problem())
     run.step(warmup)
     torch.cuda.synchronize()
-    t0, s0, _, _ = run.state()
+    _, s0, _, _ = run.state()
     stream = torch.cuda.current_stream()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    wall0 = time.perf_counter()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     ev0.record(stream)
     run.step(steps)
     ev1.record(stream)
     torch.cuda.synchronize()
-    wall = time.perf_counter() - wall0
     ms = ev0.elapsed_time(ev1)
     t1, s1, _, flags = run.state()
     if s1 - s0 != steps or flags != 0:
         raise RuntimeError(f"timed window did not run {steps} full steps ({s1 - s0}, flags {flags})")
-    return ms / steps, wall, t1
+    # per-kernel durations over a further window (events between kernels)
+    kms = run.step_timed(min(steps, 50))
+    nk = min(steps, 50)
+    run.close()
+    return ms / steps, t1, [x / nk for x in kms]
+
+
+def sod_latency(reps):
+    import torch
+    from paper_2209_01983_amd import sale
+
+    cfg = sale.make_config(64, 4, 4, hi=(1.0, 0.0625, 0.0625), t_end=0.2)
+    lat, steps = [], None
+    for _ in range(reps + 3):
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        r = sale.SaleRun(cfg, sale.sod_problem())
+        rc = r.run()
+        b = time.perf_counter()
+        if rc != sale.SALE_DONE:
+            raise RuntimeError(f"sod run ended with {rc}")
+        steps = r.state()[1]
+        r.close()
+        lat.append(b - a)
+    lat = lat[3:]
+    return {"workload": "sod 64x4x4 to t=0.2 fp64", "runs": reps, "steps": steps,
+            "p50_ms": pct(lat, 50) * 1e3, "p99_ms": pct(lat, 99) * 1e3}
+
+
+def sedov128(reps):
+    import torch
+    from paper_2209_01983_amd import sale
+
+    cfg = sale.make_config(128, 128, 128, hi=(1.2, 1.2, 1.2), t_end=1.0)
+    lat, out = [], {}
+    for k in range(reps):
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        r = sale.SaleRun(cfg, sale.sedov_problem())
+        rc = r.run()
+        b = time.perf_counter()
+        if rc != sale.SALE_DONE:
+            raise RuntimeError(f"sedov 128 run ended with {rc}")
+        if k == 0:
+            m1, e1 = r.totals()
+            out = {"steps": r.state()[1], "mass_total": m1, "energy_total": e1}
+        r.close()
+        lat.append(b - a)
+    steps = out["steps"]
+    return {"workload": "sedov 128^3 to t=1.0 fp64", "runs": reps, "latency_s": lat,
+            "p50_s": pct(lat, 50), "cell_updates_per_s": 128 ** 3 * steps / pct(lat, 50), **out}
+
+
+def batched(seq_fp64=True):
+    from paper_2209_01983_amd import sale, workloads
+    from paper_2209_01983_amd.inputs import BATCH_SEED, batch_mix
+
+    reqs = batch_mix(256, seed=BATCH_SEED)
+    steps = 200
+    # one untimed warm-up launch on a small batch (code objects, clocks)
+    workloads.run_batched(reqs[:8], 5, sale.SALE_MIXED32)
+    r32 = workloads.run_batched(reqs, steps, sale.SALE_MIXED32)
+    r32["pool"].close()
+    out = {"workload": "256 runs, edges 16..64 (seed 2209), 128 sod + 128 sedov, 200 steps, "
+                       "one persistent launch",
+           "cells_total": sum(workloads.cells(r) for r in reqs),
+           "mixed32": {"cell_updates_per_s": r32["cell_updates_per_s"], "makespan_s": r32["makespan_s"],
+                       "latency_p50_s": pct(r32["latency_s"], 50), "latency_p99_s": pct(r32["latency_s"], 99)}}
+    r64 = workloads.run_batched(reqs, steps, sale.SALE_FP64)
+    r64["pool"].close()
+    out["fp64"] = {"cell_updates_per_s": r64["cell_updates_per_s"], "makespan_s": r64["makespan_s"],
+                   "latency_p50_s": pct(r64["latency_s"], 50), "latency_p99_s": pct(r64["latency_s"], 99)}
+    if seq_fp64:
+        wall, cps, lat = workloads.run_sequential(reqs, steps, sale.SALE_FP64)
+        out["fp64_sequential_plain"] = {"cell_updates_per_s": cps, "wall_s": wall,
+                                        "latency_p50_s": pct(lat, 50), "latency_p99_s": pct(lat, 99)}
+    return out
+
+
+def serving(n_req, budget_gb):
+    from paper_2209_01983_amd import sale, workloads
+    from paper_2209_01983_amd.inputs import SERVE_SEED, serve_trace
+
+    trace = serve_trace(n_req, seed=SERVE_SEED)
+    out = {"workload": f"{n_req} requests, Poisson 50/s (seed 1983), cubic 32..192, 100..500 steps, "
+                       f"50/50 sod/sedov, budget {budget_gb:g} GB, fields copied to the host",
+           "offered_cell_updates_per_s": sum(workloads.cells(r) * r["steps"] for r in trace)
+           / trace[-1]["arrival"]}
+    for name, prec in (("mixed32", sale.SALE_MIXED32), ("fp64", sale.SALE_FP64)):
+        say("serving", name)
+        _, st = workloads.serve(trace, prec, int(budget_gb * 2 ** 30))
+        out[name] = st
+    return out
 
 
 def cpu_bench(n, steps):
-    """The FP64 oracle on this host (all cores OpenMP), one warm-up step then
-    `steps` timed steps of the same Sedov workload."""
+    """The FP64 oracle on this host (all cores, OpenMP): one warm-up step,
+    then `steps` timed steps of the same Sedov workload."""
     from oracle import oracle as orc
 
     g = orc.Grid(n, n, n, hi=(1.2, 1.2, 1.2), t_end=1.0)
@@ -95,13 +252,26 @@ def main():
         print("bench.py runs on one GPU only: the SALE step here is a single-GPU path "
               "(multi-GPU halo exchange is a design note, not built); use --gpus 1", file=sys.stderr)
         sys.exit(2)
+    from paper_2209_01983_amd import sale
+
     n = a.n
-    ms, wall, t_sim = gpu_bench(n, a.steps, a.warmup, precision=0)
-    ms32, _, _ = gpu_bench(n, a.steps, a.warmup, precision=1)
+    say("headline fp64", n)
+    ms, t_sim, k64 = headline(n, a.steps, a.warmup, sale.SALE_FP64)
+    say("headline mixed32", n)
+    ms32, _, k32 = headline(n, a.steps, a.warmup, sale.SALE_MIXED32)
     cells = n ** 3
     value = cells * 1e3 / ms
     abytes = algorithmic_bytes(n)
-    achieved = abytes / (ms * 1e-3) / 1e9
+    step_kernel_ms = sum(k64)
+    achieved = abytes / (step_kernel_ms * 1e-3) / 1e9
+    comp = compulsory_bytes(n)
+    traffic, traffic_note = measured_traffic()
+    kernels = []
+    for name, kms in (("k_begin", k64[0]), ("k_lagrange", k64[1]), ("k_remap", k64[2])):
+        b = comp.get(name)
+        kernels.append({"name": name, "avg_ms": kms,
+                        "compulsory_bytes": b, "compulsory_GBps": (b / (kms * 1e-3) / 1e9) if b else None})
+    dominant = max(kernels, key=lambda k: k["avg_ms"])
     out = {
         "metric": "cell-updates/s (Lagrange+remap) 320^3 FP64 vs FP32; p50/p99 per-run latency",
         "value": value,
@@ -115,16 +285,29 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic (Sedov blast initial state generated on the device)",
-        "config": {"workload": f"sedov {n}^3 octant, FP64 Lagrange + donor-cell remap", "cells": cells,
-                   "precision": "fp64", "sim_time_end_of_window": t_sim},
+        "config": {"workload": f"sedov {n}^3 octant of [0,1.2]^3, FP64 Lagrange + donor-cell remap, CFL 0.5",
+                   "cells": cells, "precision": "fp64", "sim_time_end_of_window": t_sim},
         "mixed32": {"value": cells * 1e3 / ms32, "unit": "cell-updates/s", "ms_per_step": ms32,
-                    "precision": "FP32 bulk, FP64 geometry/dt/totals"},
+                    "kernel_ms": k32, "precision": "FP32 bulk, FP64 geometry/volumes/dt/totals"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "whole step (all step kernels), algorithmic bytes "
-                               f"{abytes / cells:.2f} B/cell"},
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": (traffic / (step_kernel_ms * 1e-3) / 1e9) if traffic else None,
+                     "traffic_bytes_per_step": traffic, "traffic_source": traffic_note,
+                     "unit_of_work": "one step (k_begin + k_lagrange + k_remap), HIP events per kernel",
+                     "algorithmic_bytes_per_cell": abytes / cells,
+                     "step_kernel_ms": step_kernel_ms, "dominant_kernel": dominant["name"],
+                     "kernels": kernels},
     }
+    if not a.quick:
+        say("sod latency")
+        out["latency"] = sod_latency(50)
+        say("sedov 128")
+        out["sedov128"] = sedov128(3)
+        say("batched")
+        out["batched"] = batched()
+        out["serving"] = serving(a.serve_requests, a.serve_budget_gb)
     if not a.no_cpu:
+        say("cpu oracle")
         cps, threads, secs = cpu_bench(n, a.cpu_steps)
         out["cpu_baseline"] = {"value": cps, "unit": "cell-updates/s", "cores": threads, "kind": "oracle",
                                "sample": f"{a.cpu_steps} FP64 oracle steps of the same {n}^3 Sedov "

@@ -82,6 +82,9 @@ extern "C" {
 #define SALE_F_W (1u << 6)      /* nodes: z velocity                      */
 #define SALE_F_STATE (1u << 7)  /* host double[4]: t, steps, next dt, status */
 #define SALE_F_TOTALS (1u << 8) /* host double[2]: total mass, total energy */
+#define SALE_F_CLOCK (1u << 9)  /* host double[2]: device wall clock (s) at the
+                                   run's first pool advance and when its last
+                                   step completed in a pool (0: never)     */
 
 /* ---- configuration ----------------------------------------------------- */
 typedef struct {
@@ -143,6 +146,14 @@ int sale_run(sale_ctx *ctx, double t_end, int64_t max_steps);
  * are always double. STATE and TOTALS always go to host double arrays.
  * Synchronises the stream. */
 int sale_fields(sale_ctx *ctx, uint32_t mask, void *const *dst, int dst_on_device, int as_fp64);
+
+/* Enqueue n steps like sale_step and time each of the step's three kernels
+ * with HIP events on the context's stream (the paper times compute cycles
+ * only, initialisation excluded, Sec. IV): ms[0], ms[1], ms[2] receive the
+ * summed durations of the step start (dt), the Lagrangian phase with the
+ * Lagrangian geometry, and the remap, over the n steps. Synchronises the
+ * stream after every step. SALE_EINVAL for n < 1 or a NULL ms. */
+int sale_step_timed(sale_ctx *ctx, int32_t n, float ms[3]);
 
 /* Synchronise the stream and return the sticky status flags (SALE_FLAG_*).
  * Returns SALE_ETANGLE / SALE_ENUMERIC if a flag is set, else SALE_DONE if

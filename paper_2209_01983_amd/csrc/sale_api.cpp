@@ -166,7 +166,7 @@ int fields_impl(const Mesh &m, int precision, const Work<double> &w64, const Wor
                 Ctl *ctl, hipStream_t stream, uint32_t mask, void *const *dst, int dst_on_device,
                 int as_fp64) {
   if (mask && !dst) return SALE_EINVAL;
-  if (mask & ~((SALE_F_TOTALS << 1) - 1u)) return SALE_EINVAL;
+  if (mask & ~((SALE_F_CLOCK << 1) - 1u)) return SALE_EINVAL;
   const hipMemcpyKind kind = dst_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
   const bool fp64 = precision == SALE_FP64;
   double *scratch = fp64 ? w64.scratch : w32.scratch;
@@ -176,7 +176,7 @@ int fields_impl(const Mesh &m, int precision, const Work<double> &w64, const Wor
     if (e_ != hipSuccess) return hip_fail(e_, #expr); \
   } while (0)
   int slot = 0;
-  for (uint32_t bit = 1; bit <= SALE_F_TOTALS; bit <<= 1) {
+  for (uint32_t bit = 1; bit <= SALE_F_CLOCK; bit <<= 1) {
     if (!(mask & bit)) continue;
     void *d = dst[slot++];
     if (!d) return SALE_EINVAL;
@@ -232,6 +232,16 @@ int fields_impl(const Mesh &m, int precision, const Work<double> &w64, const Wor
       if (rc != SALE_OK) return rc;
       ((double *)d)[0] = c.totals[0];
       ((double *)d)[1] = c.totals[1];
+    } else if (bit == SALE_F_CLOCK) {
+      Ctl c;
+      int rc = read_ctl(stream, ctl, &c);
+      if (rc != SALE_OK) return rc;
+      int dev = 0, khz = 0;
+      HIP_TRY_F(hipGetDevice(&dev));
+      HIP_TRY_F(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+      const double hz = khz > 0 ? 1e3 * khz : 1e8;
+      ((double *)d)[0] = (double)c.clk_first / hz;
+      ((double *)d)[1] = (double)c.clk_last / hz;
     }
   }
   HIP_TRY_F(hipStreamSynchronize(stream));
@@ -651,3 +661,28 @@ int sale_pool_release(sale_pool *p, int32_t slot) {
 void sale_pool_destroy(sale_pool *p) { delete p; }
 
 }  // extern "C"
+
+extern "C" int sale_step_timed(sale_ctx *x, int32_t n, float ms[3]) {
+  if (!x || n < 1 || !ms) return SALE_EINVAL;
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  hipError_t e = hipSuccess;
+  for (int k = 0; k < 4 && e == hipSuccess; k++) e = hipEventCreate(&ev[k]);
+  double acc[3] = {0.0, 0.0, 0.0};
+  for (int32_t i = 0; i < n && e == hipSuccess; i++) {
+    e = x->precision == SALE_FP64 ? sale::launch_step<double>(x->m, x->ctl, x->w64, x->cur, x->stream, ev)
+                                  : sale::launch_step<float>(x->m, x->ctl, x->w32, x->cur, x->stream, ev);
+    if (e != hipSuccess) break;
+    x->cur ^= 1;
+    e = hipEventSynchronize(ev[3]);
+    for (int k = 0; k < 3 && e == hipSuccess; k++) {
+      float t = 0.f;
+      e = hipEventElapsedTime(&t, ev[k], ev[k + 1]);
+      acc[k] += t;
+    }
+  }
+  for (int k = 0; k < 4; k++)
+    if (ev[k]) (void)hipEventDestroy(ev[k]);
+  if (e != hipSuccess) return hip_fail(e, "sale_step_timed");
+  for (int k = 0; k < 3; k++) ms[k] = (float)acc[k];
+  return SALE_OK;
+}

@@ -37,7 +37,9 @@ struct Ctl {
   unsigned int tiles_done;  // persistent kernel: finished tiles of the current phase
   unsigned int phase;       // persistent kernel: phase counter of the run
   long long step_target;    // persistent kernel: stop after this many steps
-  double pad[3];
+  long long clk_first;      // persistent kernel: device wall clock at the run's first advance
+  long long clk_last;       // persistent kernel: device wall clock when its last step completed
+  double pad;
 };
 
 // One copy of the state, logical layout (see include/sale.h). R is the
@@ -115,8 +117,11 @@ hipError_t launch_init_user(const Mesh &m, Ctl *ctl, const Work<R> &w, const dou
 
 hipError_t launch_set_t_end(Ctl *ctl, double t_end, hipStream_t s);
 // One step from w.s[cur] into w.s[1 - cur].
+// With `ev` (4 events), ev[0..3] are recorded before the step and after each
+// of its three kernels (start, Lagrange+geometry, remap).
 template <typename R>
-hipError_t launch_step(const Mesh &m, Ctl *ctl, const Work<R> &w, int cur, hipStream_t s);
+hipError_t launch_step(const Mesh &m, Ctl *ctl, const Work<R> &w, int cur, hipStream_t s,
+                       const hipEvent_t *ev = nullptr);
 template <typename R>
 hipError_t launch_totals(const Mesh &m, Ctl *ctl, const Work<R> &w, int cur, hipStream_t s);
 // Step arguments of one run (state w.s[cur] -> w.s[1 - cur]); the kernels'

@@ -73,6 +73,7 @@ __global__ void k_pool_prepare(PoolRun<R> *runs, const int *act, PoolQueue *qh) 
   c->tiles_done = 0u;
   c->phase = 0u;
   c->step_target = p.step_target;
+  if (c->clk_first == 0) c->clk_first = wall_clock64();
   begin_step(p.m, c, p.step_target);
 }
 
@@ -137,7 +138,8 @@ __global__ __launch_bounds__(NT, SALE_WAVES_POOL) void k_pool(PoolRun<R> *runs, 
       s_go = go;
     }
     __syncthreads();
-    if (s_go && !__hip_atomic_load(&ctl->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+    const bool ran = s_go && !__hip_atomic_load(&ctl->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (ran) {
       const RunArgs<R> a = args_of(p);
       if (!remap) {
         const bool t = lagrange_tile<R, CH>(a, tile, ctl->dt, lds);
@@ -159,6 +161,7 @@ __global__ __launch_bounds__(NT, SALE_WAVES_POOL) void k_pool(PoolRun<R> *runs, 
       if (old == ntiles - 1u) {
         __atomic_thread_fence(__ATOMIC_ACQUIRE);
         atomicExch(&ctl->tiles_done, 0u);
+        if (remap && ran) ctl->clk_last = wall_clock64();  // the step just completed
         // the next advance's prepare starts the step after the last round
         if (remap && round + 1 < rounds) begin_step(p.m, ctl, p.step_target);
         __threadfence();

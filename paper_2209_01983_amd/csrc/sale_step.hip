@@ -118,6 +118,8 @@ __global__ void k_ctl_init(Ctl *ctl, double t0, long long step0, double t_end) {
   ctl->tiles_done = 0u;
   ctl->phase = 0u;
   ctl->step_target = 0;
+  ctl->clk_first = 0;
+  ctl->clk_last = 0;
 }
 
 __global__ void k_set_t_end(Ctl *ctl, double t_end) {
@@ -406,12 +408,18 @@ RunArgs<R> run_args(const Mesh &m, Ctl *ctl, const Work<R> &w, int cur, int targ
 }
 
 template <typename R>
-hipError_t launch_step(const Mesh &m, Ctl *ctl, const Work<R> &w, int cur, hipStream_t s) {
+hipError_t launch_step(const Mesh &m, Ctl *ctl, const Work<R> &w, int cur, hipStream_t s, const hipEvent_t *ev) {
   const RunArgs<R> a = run_args<R>(m, ctl, w, cur, 3072);
+  hipError_t e = hipSuccess;
+  if (ev) e = hipEventRecord(ev[0], s);
   hipLaunchKernelGGL(k_begin, dim3(1), dim3(64), 0, s, m, ctl);
+  if (ev && e == hipSuccess) e = hipEventRecord(ev[1], s);
   hipLaunchKernelGGL(k_lagrange<R>, dim3(a.ga.blocks()), dim3(kStepThreads), 0, s, a);
+  if (ev && e == hipSuccess) e = hipEventRecord(ev[2], s);
   hipLaunchKernelGGL(k_remap<R>, dim3(a.gb.blocks()), dim3(kStepThreads), 0, s, a);
-  return hipGetLastError();
+  if (ev && e == hipSuccess) e = hipEventRecord(ev[3], s);
+  const hipError_t l = hipGetLastError();
+  return l != hipSuccess ? l : e;
 }
 
 template <typename R>
@@ -438,7 +446,8 @@ hipError_t launch_export(const Mesh &m, const Work<R> &w, int cur, int which, do
   template hipError_t launch_init_user<R>(const Mesh &, Ctl *, const Work<R> &, const double *const[5],  \
                                           bool, double, long long, double, hipStream_t);                 \
   template RunArgs<R> run_args<R>(const Mesh &, Ctl *, const Work<R> &, int, int);                       \
-  template hipError_t launch_step<R>(const Mesh &, Ctl *, const Work<R> &, int, hipStream_t);            \
+  template hipError_t launch_step<R>(const Mesh &, Ctl *, const Work<R> &, int, hipStream_t,                \
+                                    const hipEvent_t *);                                                 \
   template hipError_t launch_totals<R>(const Mesh &, Ctl *, const Work<R> &, int, hipStream_t);          \
   template hipError_t launch_export<R>(const Mesh &, const Work<R> &, int, int, double *, hipStream_t);
 SALE_INSTANTIATE(double)

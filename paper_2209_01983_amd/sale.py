@@ -28,7 +28,7 @@ SALE_SOD_X, SALE_SEDOV_CORNER, SALE_USER = 0, 1, 2
 SALE_FLAG_TANGLE, SALE_FLAG_NUMERIC = 1, 2
 SALE_F_RHO, SALE_F_E, SALE_F_P, SALE_F_Q = 1 << 0, 1 << 1, 1 << 2, 1 << 3
 SALE_F_U, SALE_F_V, SALE_F_W = 1 << 4, 1 << 5, 1 << 6
-SALE_F_STATE, SALE_F_TOTALS = 1 << 7, 1 << 8
+SALE_F_STATE, SALE_F_TOTALS, SALE_F_CLOCK = 1 << 7, 1 << 8, 1 << 9
 
 FIELD_BITS = {"rho": SALE_F_RHO, "e": SALE_F_E, "p": SALE_F_P, "q": SALE_F_Q,
               "u": SALE_F_U, "v": SALE_F_V, "w": SALE_F_W}
@@ -37,7 +37,7 @@ NODE_FIELDS = ("u", "v", "w")
 
 # functions the header declares (checked by the tests against include/sale.h)
 EXPORTS = ("sale_workspace_bytes", "sale_init", "sale_step", "sale_run", "sale_fields",
-           "sale_status", "sale_destroy", "sale_strerror")
+           "sale_step_timed", "sale_status", "sale_destroy", "sale_strerror")
 POOL_EXPORTS = ("sale_pool_create", "sale_pool_admit", "sale_pool_advance", "sale_pool_poll",
                 "sale_pool_fields", "sale_pool_release", "sale_pool_destroy")
 
@@ -86,6 +86,8 @@ def lib():
         L.sale_run.restype = C.c_int
         L.sale_fields.argtypes = [C.c_void_p, C.c_uint32, C.POINTER(C.c_void_p), C.c_int, C.c_int]
         L.sale_fields.restype = C.c_int
+        L.sale_step_timed.argtypes = [C.c_void_p, C.c_int32, C.POINTER(C.c_float)]
+        L.sale_step_timed.restype = C.c_int
         L.sale_status.argtypes = [C.c_void_p, C.POINTER(C.c_int32)]
         L.sale_status.restype = C.c_int
         L.sale_destroy.argtypes = [C.c_void_p]
@@ -140,6 +142,13 @@ def sale_run(ctx, t_end: float, max_steps: int) -> int:
 def sale_fields(ctx, mask: int, dst_ptrs, dst_on_device: int, as_fp64: int) -> int:
     arr = (C.c_void_p * max(1, len(dst_ptrs)))(*[C.c_void_p(p) for p in dst_ptrs])
     return lib().sale_fields(ctx, mask, arr, dst_on_device, as_fp64)
+
+
+def sale_step_timed(ctx, n: int):
+    """Returns (code, [ms start, ms Lagrange+geometry, ms remap]) summed over n steps."""
+    ms = (C.c_float * 3)()
+    rc = lib().sale_step_timed(ctx, n, ms)
+    return rc, [float(x) for x in ms]
 
 
 def sale_status(ctx):
@@ -294,6 +303,13 @@ class SaleRun:
             if rc != SALE_OK:
                 raise SaleError(rc, "sale_step")
 
+    def step_timed(self, n=1):
+        """n steps; per-kernel durations (ms) summed over them."""
+        rc, ms = sale_step_timed(self.ctx, n)
+        if rc != SALE_OK:
+            raise SaleError(rc, "sale_step_timed")
+        return ms
+
     def run(self, t_end=-1.0, max_steps=1 << 40) -> int:
         return sale_run(self.ctx, t_end, max_steps)
 
@@ -392,6 +408,14 @@ class Pool:
         if rc != SALE_OK:
             raise SaleError(rc, "sale_pool_fields")
         return float(o[0]), int(o[1]), float(o[2]), int(o[3])
+
+    def clock(self, slot):
+        """(first advance, last completed step) of a slot, device wall clock in s."""
+        o = np.zeros(2)
+        rc = sale_pool_fields(self.pool, slot, SALE_F_CLOCK, [o.ctypes.data], 0, 1)
+        if rc != SALE_OK:
+            raise SaleError(rc, "sale_pool_fields")
+        return float(o[0]), float(o[1])
 
     def release(self, slot):
         rc = sale_pool_release(self.pool, slot)

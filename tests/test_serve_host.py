@@ -1,0 +1,111 @@
+"""Host logic of the continuous-batching server (no GPU): FIFO admission
+under a budget, slicing, completion, release and latency accounting, with
+the pool replaced by a stand-in that only counts steps."""
+import pytest
+
+from paper_2209_01983_amd import sale, workloads
+
+
+class CountingPool:
+    """Stand-in for sale.Pool: a run needs `cells` bytes of the budget and
+    finishes after its step count; nothing is computed."""
+    log = []
+
+    def __init__(self, budget, max_runs, precision):
+        self.budget, self.max_runs, self.used = budget, max_runs, 0
+        self.runs = {}
+
+    def admit(self, cfg, prob, n_steps):
+        need = cfg.nx * cfg.ny * cfg.nz
+        if self.used + need > self.budget or len(self.runs) >= self.max_runs:
+            return None
+        slot = min(set(range(self.max_runs)) - set(self.runs))
+        self.runs[slot] = [need, n_steps, 0]
+        self.used += need
+        CountingPool.log.append(("admit", slot, cfg.nx))
+        return slot
+
+    def advance(self, k):
+        for r in self.runs.values():
+            r[2] = min(r[1], r[2] + k)
+
+    def poll(self):
+        out = [s for s, r in self.runs.items() if r[2] >= r[1] and len(r) == 3]
+        for s in out:
+            self.runs[s].append("reported")
+        return out
+
+    def fields(self, slot):
+        return {"steps": self.runs[slot][2]}
+
+    def state(self, slot):
+        r = self.runs[slot]
+        return 0.0, r[2], 0.0, 0
+
+    def release(self, slot):
+        self.used -= self.runs.pop(slot)[0]
+
+    def close(self):
+        pass
+
+
+class FakeClock:
+    def __init__(self):
+        self.t = 0.0
+
+    def __call__(self):
+        self.t += 1e-4
+        return self.t
+
+    def sleep(self, dt):
+        self.t += dt
+
+
+def trace_of(sizes_steps, gap=0.01):
+    return [{"arrival": gap * i, "kind": "sedov", "n": (n, n, n), "steps": s, "edep": 0.5}
+            for i, (n, s) in enumerate(sizes_steps)]
+
+
+def test_fifo_admission_under_budget_and_latency_accounting(monkeypatch):
+    monkeypatch.setattr(sale, "Pool", CountingPool)
+    CountingPool.log = []
+    tr = trace_of([(4, 10), (4, 30), (4, 5), (2, 5), (3, 7)])
+    clk = FakeClock()
+    # budget: two 4^3 runs at once
+    served, st = workloads.serve(tr, sale.SALE_FP64, 2 * 64 + 10, max_runs=4, slice_steps=5, clock=clk,
+                                 sleep=clk.sleep)
+    assert [s.index for s in served] == [0, 1, 2, 3, 4]
+    assert all(s.fields["steps"] == tr[s.index]["steps"] for s in served)
+    admitted = [e[2] for e in CountingPool.log]
+    assert admitted == [4, 4, 4, 2, 3]          # FIFO: request 3 does not overtake request 2
+    for s in served:
+        assert s.arrival <= s.admitted <= s.finished
+    assert served[2].admitted > served[2].arrival  # waited for memory
+    assert st["requests"] == 5 and st["latency_p99_s"] >= st["latency_p50_s"] > 0
+    assert st["cell_updates_per_s"] > 0
+
+
+def test_idle_server_sleeps_until_the_next_arrival(monkeypatch):
+    monkeypatch.setattr(sale, "Pool", CountingPool)
+    tr = trace_of([(2, 3), (2, 3)], gap=5.0)
+    clk = FakeClock()
+    served, st = workloads.serve(tr, sale.SALE_FP64, 1000, clock=clk, sleep=clk.sleep)
+    assert served[1].admitted >= 5.0 and st["launches"] == 2
+
+
+def test_request_larger_than_the_budget_is_an_error(monkeypatch):
+    monkeypatch.setattr(sale, "Pool", CountingPool)
+    tr = trace_of([(8, 3)])
+    clk = FakeClock()
+    with pytest.raises(RuntimeError, match="does not fit"):
+        workloads.serve(tr, sale.SALE_FP64, 100, clock=clk, sleep=clk.sleep)
+
+
+def test_request_geometry_follows_the_stated_setup():
+    cfg, prob = workloads.request_problem({"kind": "sod", "n": (40, 8, 4), "rho_ratio": 8.0, "p_ratio": 10.0},
+                                          sale.SALE_MIXED32)
+    assert tuple(cfg.hi) == pytest.approx((1.0, 0.2, 0.1)) and cfg.precision == sale.SALE_MIXED32
+    assert list(prob.sod) == pytest.approx([0.5, 1.0, 1.0, 0.125, 0.1])
+    cfg, prob = workloads.request_problem({"kind": "sedov", "n": (20, 40, 30), "edep": 0.3}, sale.SALE_FP64)
+    assert tuple(cfg.hi) == pytest.approx((0.6, 1.2, 0.9))
+    assert list(prob.sedov) == pytest.approx([1.0, 1e-6, 0.3])
