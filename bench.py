@@ -59,6 +59,8 @@ def parse():
     ap.add_argument("--cpu-steps", type=int, default=10)
     ap.add_argument("--serve-requests", type=int, default=1000)
     ap.add_argument("--serve-budget-gb", type=float, default=64.0)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run one plain device copy of 2 GiB (reference for HBM counters)")
     return ap.parse_args()
 
 
@@ -228,6 +230,18 @@ def serving(n_req, budget_gb):
     return out
 
 
+def copy_calibration(nbytes=2 << 30):
+    """One plain device-to-device copy kernel of `nbytes` (read nbytes, write
+    nbytes): the reference that scales the HBM byte counters."""
+    import torch
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    say("copy calibration", nbytes, "bytes")
+
+
 def cpu_bench(n, steps):
     """The FP64 oracle on this host (all cores, OpenMP): one warm-up step,
     then `steps` timed steps of the same Sedov workload."""
@@ -254,6 +268,8 @@ def main():
         sys.exit(2)
     from paper_2209_01983_amd import sale
 
+    if a.copy_calibration:
+        copy_calibration()
     n = a.n
     say("headline fp64", n)
     ms, t_sim, k64 = headline(n, a.steps, a.warmup, sale.SALE_FP64)
