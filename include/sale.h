@@ -134,9 +134,12 @@ int sale_step(sale_ctx *ctx);
 
 /* Run until t >= t_end or until max_steps more steps were taken. t_end < 0
  * keeps the configured end time; otherwise it replaces it (the last step is
- * clipped to land on it). Synchronises the stream every few steps to read the
- * device status. Returns SALE_DONE when t_end was reached, SALE_OK when
- * max_steps ran out first, SALE_ETANGLE / SALE_ENUMERIC on a flagged step. */
+ * clipped to land on it). Steps are enqueued in chunks, mostly as replays of
+ * a captured HIP graph of several steps (dt, t and the done decision stay in
+ * device memory, so a replay past t_end is a no-op); the stream is
+ * synchronised after each chunk to read the device status. Returns SALE_DONE
+ * when t_end was reached, SALE_OK when max_steps ran out first,
+ * SALE_ETANGLE / SALE_ENUMERIC on a flagged step. */
 int sale_run(sale_ctx *ctx, double t_end, int64_t max_steps);
 
 /* Copy the fields selected by `mask` into dst[0..], one pointer per set bit in

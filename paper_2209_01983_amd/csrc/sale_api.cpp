@@ -28,7 +28,20 @@ struct sale_ctx {
   Work<float> w32;
   int cur;  // which of the two state buffers holds the current state
   double t_end;
+  // step graphs: kGraphSteps steps captured once per starting buffer parity
+  // on a private capture stream, replayed on `stream` by sale_run
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t graph[2] = {nullptr, nullptr};
+  ~sale_ctx() {
+    for (int k = 0; k < 2; k++)
+      if (graph[k]) (void)hipGraphExecDestroy(graph[k]);
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
+  }
 };
+
+// Steps per captured graph (even, so that a replay leaves the current state
+// in the buffer it started from).
+constexpr int kGraphSteps = 8;
 
 namespace sale_host {
 
@@ -159,6 +172,49 @@ hipError_t enqueue_step(sale_ctx *x) {
                                            : sale::launch_step<float>(x->m, x->ctl, x->w32, x->cur, x->stream);
   if (e == hipSuccess) x->cur ^= 1;
   return e;
+}
+
+// The graph of kGraphSteps steps starting from state buffer `par`, captured on
+// first use. The step kernels take every run-time quantity (dt, t, the done
+// decision) from the control block, so one capture serves every replay.
+hipError_t step_graph(sale_ctx *x, int par, hipGraphExec_t *out) {
+  if (!x->graph[par]) {
+    hipError_t e = hipSuccess;
+    if (!x->cap_stream) e = hipStreamCreateWithFlags(&x->cap_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) return e;
+    e = hipStreamBeginCapture(x->cap_stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return e;
+    hipError_t le = hipSuccess;
+    for (int s = 0; s < kGraphSteps && le == hipSuccess; s++)
+      le = x->precision == SALE_FP64 ? sale::launch_step<double>(x->m, x->ctl, x->w64, par ^ (s & 1), x->cap_stream)
+                                     : sale::launch_step<float>(x->m, x->ctl, x->w32, par ^ (s & 1), x->cap_stream);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(x->cap_stream, &g);
+    if (le != hipSuccess) e = le;
+    if (e == hipSuccess) e = hipGraphInstantiate(&x->graph[par], g, nullptr, nullptr, 0);
+    if (g) (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+      x->graph[par] = nullptr;
+      return e;
+    }
+  }
+  *out = x->graph[par];
+  return hipSuccess;
+}
+
+// n steps on the context's stream: whole graphs, then single steps.
+hipError_t enqueue_steps(sale_ctx *x, int64_t n) {
+  for (; n >= kGraphSteps; n -= kGraphSteps) {
+    hipGraphExec_t g;
+    hipError_t e = step_graph(x, x->cur, &g);
+    if (e == hipSuccess) e = hipGraphLaunch(g, x->stream);
+    if (e != hipSuccess) return e;
+  }
+  for (; n > 0; n--) {
+    hipError_t e = enqueue_step(x);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 // Field export shared by single runs and pool slots (see sale_fields).
@@ -328,7 +384,7 @@ int sale_run(sale_ctx *x, double t_end, int64_t max_steps) {
   int64_t chunk = 4;
   while (left > 0) {
     const int64_t n = std::min(left, chunk);
-    for (int64_t s = 0; s < n; s++) HIP_TRY(enqueue_step(x));
+    HIP_TRY(enqueue_steps(x, n));
     left -= n;
     if ((rc = read_ctl(x->stream, x->ctl, &c)) != SALE_OK) return rc;
     if ((rc = status_code(c)) != SALE_OK) return rc;
@@ -339,6 +395,7 @@ int sale_run(sale_ctx *x, double t_end, int64_t max_steps) {
       const double per = (c.t - last_t) / (double)took;
       const double est = (c.t_end - c.t) / per;
       chunk = (int64_t)std::max(1.0, std::min(256.0, 0.9 * est));
+      if (chunk >= kGraphSteps) chunk -= chunk % kGraphSteps;  // whole graphs
     }
     last_step = c.step;
     last_t = c.t;

@@ -353,3 +353,41 @@ def test_mixed32_sedov_conservation_and_agreement_with_fp64():
         l1 = np.abs(f32[k] - f64[k]).sum() / np.abs(f64[k]).sum()
         assert l1 <= 1e-4, (k, l1)
     say("mixed32 sedov48 drift", dm32, de32)
+
+
+# ---------------------------------------------------------------------------
+# step graphs: sale_run replays captured multi-step graphs
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("precision", [sale.SALE_FP64, sale.SALE_MIXED32])
+def test_graph_replays_are_bitwise_the_eager_steps(precision):
+    say("graph vs eager, precision", precision)
+    cfg = sale.make_config(40, 36, 33, hi=(1.2, 1.08, 0.99), t_end=0.02, precision=precision)
+    # eager: one step at a time until t_end
+    e = sale.SaleRun(cfg, sale.sedov_problem())
+    n = 0
+    while e.state()[0] < 0.02:
+        e.step()
+        n += 1
+    assert n > 40, n          # several graph replays of the run below
+    # graph path, in pieces with eager work and reads between the replays
+    g = sale.SaleRun(cfg, sale.sedov_problem())
+    assert g.run(max_steps=17) == sale.SALE_OK      # graphs + single steps, odd count
+    mid = g.fields()
+    g.step(3)
+    assert g.run(max_steps=24) == sale.SALE_OK
+    assert g.run() == sale.SALE_DONE
+    assert g.state()[:2] == e.state()[:2] and g.state()[1] == n
+    ref, got = e.fields(), g.fields()
+    for k in FIELDS:
+        assert np.array_equal(got[k], ref[k]), k
+    # the replays past t_end changed nothing
+    assert g.run(t_end=0.02, max_steps=16) == sale.SALE_DONE
+    again = g.fields()
+    for k in FIELDS:
+        assert np.array_equal(again[k], ref[k]), k
+    # the intermediate read came from a consistent state: re-run eagerly to step 17
+    h = sale.SaleRun(cfg, sale.sedov_problem())
+    h.step(17)
+    hf = h.fields()
+    for k in FIELDS:
+        assert np.array_equal(hf[k], mid[k]), k
