@@ -59,6 +59,7 @@ def parse():
     ap.add_argument("--cpu-steps", type=int, default=10)
     ap.add_argument("--serve-requests", type=int, default=1000)
     ap.add_argument("--serve-budget-gb", type=float, default=64.0)
+    ap.add_argument("--no-tune", action="store_true", help="default launch shape, no autotuning")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run one plain device copy of 2 GiB (reference for HBM counters)")
     return ap.parse_args()
@@ -115,13 +116,20 @@ def measured_traffic():
 
 
 # ---- workloads -----------------------------------------------------------------
-def headline(n, steps, warmup, precision):
-    """(ms per step from HIP events around `steps` async steps, final t)."""
+def headline(n, steps, warmup, precision, tuned=True):
+    """(ms per step from HIP events around `steps` async steps, final t,
+    per-kernel ms, launch shape). With `tuned`, the autotuner first picks the
+    launch shape of the step kernels for this mesh and precision."""
     import torch
-    from paper_2209_01983_amd import sale
+    from paper_2209_01983_amd import sale, tune
 
     cfg = sale.make_config(n, n, n, hi=(1.2, 1.2, 1.2), t_end=1.0, precision=precision)
+    shape = {"rows_a": 16, "rows_b": 16, "target": 3072}
+    if tuned:
+        best = tune.tune(cfg, steps=4, warmup=1, save=False)
+        shape = {k: best[k] for k in ("rows_a", "rows_b", "target")}
     run = sale.SaleRun(cfg, sale.sedov_problem())
+    run.set_launch(shape["rows_a"], shape["rows_b"], shape["target"])
     run.step(warmup)
     torch.cuda.synchronize()
     _, s0, _, _ = run.state()
@@ -139,7 +147,7 @@ def headline(n, steps, warmup, precision):
     kms = run.step_timed(min(steps, 50))
     nk = min(steps, 50)
     run.close()
-    return ms / steps, t1, [x / nk for x in kms]
+    return ms / steps, t1, [x / nk for x in kms], shape
 
 
 def sod_latency(reps):
@@ -272,9 +280,9 @@ def main():
         copy_calibration()
     n = a.n
     say("headline fp64", n)
-    ms, t_sim, k64 = headline(n, a.steps, a.warmup, sale.SALE_FP64)
+    ms, t_sim, k64, shape64 = headline(n, a.steps, a.warmup, sale.SALE_FP64, tuned=not a.no_tune)
     say("headline mixed32", n)
-    ms32, _, k32 = headline(n, a.steps, a.warmup, sale.SALE_MIXED32)
+    ms32, _, k32, shape32 = headline(n, a.steps, a.warmup, sale.SALE_MIXED32, tuned=not a.no_tune)
     cells = n ** 3
     value = cells * 1e3 / ms
     abytes = algorithmic_bytes(n)
@@ -302,9 +310,11 @@ def main():
         "dtype": "f64",
         "data": "synthetic (Sedov blast initial state generated on the device)",
         "config": {"workload": f"sedov {n}^3 octant of [0,1.2]^3, FP64 Lagrange + donor-cell remap, CFL 0.5",
-                   "cells": cells, "precision": "fp64", "sim_time_end_of_window": t_sim},
+                   "cells": cells, "precision": "fp64", "sim_time_end_of_window": t_sim,
+                   "launch_shape": shape64},
         "mixed32": {"value": cells * 1e3 / ms32, "unit": "cell-updates/s", "ms_per_step": ms32,
-                    "kernel_ms": k32, "precision": "FP32 bulk, FP64 geometry/volumes/dt/totals"},
+                    "kernel_ms": k32, "launch_shape": shape32,
+                    "precision": "FP32 bulk, FP64 geometry/volumes/dt/totals"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": (traffic / (step_kernel_ms * 1e-3) / 1e9) if traffic else None,

@@ -158,6 +158,13 @@ int sale_fields(sale_ctx *ctx, uint32_t mask, void *const *dst, int dst_on_devic
  * stream after every step. SALE_EINVAL for n < 1 or a NULL ms. */
 int sale_step_timed(sale_ctx *ctx, int32_t n, float ms[3]);
 
+/* Launch shape of the context's two step kernels (a tuning knob; results do
+ * not depend on it): tiles of 32 x rows columns for the Lagrangian kernel and
+ * the remap kernel (rows 8, 16 or 32; default 16 and 16), and the number of
+ * blocks the split of the z extent into segments aims at (default 3072).
+ * Synchronises the stream. SALE_EINVAL for other values. */
+int sale_set_launch(sale_ctx *ctx, int32_t rows_lagrange, int32_t rows_remap, int32_t target_blocks);
+
 /* Synchronise the stream and return the sticky status flags (SALE_FLAG_*).
  * Returns SALE_ETANGLE / SALE_ENUMERIC if a flag is set, else SALE_DONE if
  * t >= t_end, else SALE_OK. */

@@ -28,6 +28,7 @@ struct sale_ctx {
   Work<float> w32;
   int cur;  // which of the two state buffers holds the current state
   double t_end;
+  sale::Launch L;  // launch shape of the step kernels
   // step graphs: kGraphSteps steps captured once per starting buffer parity
   // on a private capture stream, replayed on `stream` by sale_run
   hipStream_t cap_stream = nullptr;
@@ -168,8 +169,8 @@ double next_dt(const Ctl &c, const Mesh &m) {
 // (after t_end or an error) copies the state across, so the current state is
 // always in buffer `cur` as the host counts it.
 hipError_t enqueue_step(sale_ctx *x) {
-  hipError_t e = x->precision == SALE_FP64 ? sale::launch_step<double>(x->m, x->ctl, x->w64, x->cur, x->stream)
-                                           : sale::launch_step<float>(x->m, x->ctl, x->w32, x->cur, x->stream);
+  hipError_t e = x->precision == SALE_FP64 ? sale::launch_step<double>(x->m, x->ctl, x->w64, x->cur, x->L, x->stream)
+                                           : sale::launch_step<float>(x->m, x->ctl, x->w32, x->cur, x->L, x->stream);
   if (e == hipSuccess) x->cur ^= 1;
   return e;
 }
@@ -186,8 +187,8 @@ hipError_t step_graph(sale_ctx *x, int par, hipGraphExec_t *out) {
     if (e != hipSuccess) return e;
     hipError_t le = hipSuccess;
     for (int s = 0; s < kGraphSteps && le == hipSuccess; s++)
-      le = x->precision == SALE_FP64 ? sale::launch_step<double>(x->m, x->ctl, x->w64, par ^ (s & 1), x->cap_stream)
-                                     : sale::launch_step<float>(x->m, x->ctl, x->w32, par ^ (s & 1), x->cap_stream);
+      le = x->precision == SALE_FP64 ? sale::launch_step<double>(x->m, x->ctl, x->w64, par ^ (s & 1), x->L, x->cap_stream)
+                                     : sale::launch_step<float>(x->m, x->ctl, x->w32, par ^ (s & 1), x->L, x->cap_stream);
     hipGraph_t g = nullptr;
     e = hipStreamEndCapture(x->cap_stream, &g);
     if (le != hipSuccess) e = le;
@@ -524,8 +525,8 @@ sale::PoolRun<R> pool_image(const PoolSlot &sl, const Work<R> &w) {
   r.wp = w.wp;
   r.geo = w.geo;
   // one z segment per tile: the pool's parallelism comes from its many runs
-  r.ga = sale::grid_lagrange(sl.m, 1);
-  r.gb = sale::grid_remap(sl.m, 1);
+  r.ga = sale::grid_lagrange(sl.m, 1, 16);
+  r.gb = sale::grid_remap(sl.m, 1, 16);
   r.step0 = sl.step0;
   r.step_target = sl.step_target;
   return r;
@@ -726,8 +727,8 @@ extern "C" int sale_step_timed(sale_ctx *x, int32_t n, float ms[3]) {
   for (int k = 0; k < 4 && e == hipSuccess; k++) e = hipEventCreate(&ev[k]);
   double acc[3] = {0.0, 0.0, 0.0};
   for (int32_t i = 0; i < n && e == hipSuccess; i++) {
-    e = x->precision == SALE_FP64 ? sale::launch_step<double>(x->m, x->ctl, x->w64, x->cur, x->stream, ev)
-                                  : sale::launch_step<float>(x->m, x->ctl, x->w32, x->cur, x->stream, ev);
+    e = x->precision == SALE_FP64 ? sale::launch_step<double>(x->m, x->ctl, x->w64, x->cur, x->L, x->stream, ev)
+                                  : sale::launch_step<float>(x->m, x->ctl, x->w32, x->cur, x->L, x->stream, ev);
     if (e != hipSuccess) break;
     x->cur ^= 1;
     e = hipEventSynchronize(ev[3]);
@@ -741,5 +742,23 @@ extern "C" int sale_step_timed(sale_ctx *x, int32_t n, float ms[3]) {
     if (ev[k]) (void)hipEventDestroy(ev[k]);
   if (e != hipSuccess) return hip_fail(e, "sale_step_timed");
   for (int k = 0; k < 3; k++) ms[k] = (float)acc[k];
+  return SALE_OK;
+}
+
+extern "C" int sale_set_launch(sale_ctx *x, int32_t rows_lagrange, int32_t rows_remap, int32_t target_blocks) {
+  if (!x) return SALE_EINVAL;
+  sale::Launch L;
+  L.rows_a = rows_lagrange;
+  L.rows_b = rows_remap;
+  L.target = target_blocks;
+  if (!sale::launch_valid(L)) return SALE_EINVAL;
+  // captured step graphs hold the old shape; wait for replays in flight first
+  HIP_TRY(hipStreamSynchronize(x->stream));
+  for (int k = 0; k < 2; k++)
+    if (x->graph[k]) {
+      (void)hipGraphExecDestroy(x->graph[k]);
+      x->graph[k] = nullptr;
+    }
+  x->L = L;
   return SALE_OK;
 }

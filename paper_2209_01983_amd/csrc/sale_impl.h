@@ -93,9 +93,19 @@ struct RunArgs {
   Grid2 ga, gb;  // decompositions of the Lagrange and remap kernels
 };
 
-Grid2 grid_lagrange(const Mesh &m, int target_blocks);
-Grid2 grid_remap(const Mesh &m, int target_blocks);
-constexpr int kStepThreads = 512;  // block size of both z-marching kernels
+// Launch shape of the two z-marching kernels of a single run: tile rows
+// (tiles are 32 x rows columns, one thread per column; rows 8, 16 or 32) and
+// the number of blocks the z segmentation aims at.
+struct Launch {
+  int rows_a = 16;     // Lagrange + geometry kernel
+  int rows_b = 16;     // remap kernel
+  int target = 3072;   // blocks per kernel the z split aims at
+};
+bool launch_valid(const Launch &L);
+
+Grid2 grid_lagrange(const Mesh &m, int target_blocks, int rows);
+Grid2 grid_remap(const Mesh &m, int target_blocks, int rows);
+constexpr int kStepThreads = 512;  // block size of the 16-row tiles (and of the pool kernel)
 
 template <typename R>
 size_t workspace_bytes(const Mesh &m);
@@ -120,14 +130,13 @@ hipError_t launch_set_t_end(Ctl *ctl, double t_end, hipStream_t s);
 // With `ev` (4 events), ev[0..3] are recorded before the step and after each
 // of its three kernels (start, Lagrange+geometry, remap).
 template <typename R>
-hipError_t launch_step(const Mesh &m, Ctl *ctl, const Work<R> &w, int cur, hipStream_t s,
+hipError_t launch_step(const Mesh &m, Ctl *ctl, const Work<R> &w, int cur, const Launch &L, hipStream_t s,
                        const hipEvent_t *ev = nullptr);
 template <typename R>
 hipError_t launch_totals(const Mesh &m, Ctl *ctl, const Work<R> &w, int cur, hipStream_t s);
-// Step arguments of one run (state w.s[cur] -> w.s[1 - cur]); the kernels'
-// z segmentation aims at `target_blocks` blocks per kernel.
+// Step arguments of one run (state w.s[cur] -> w.s[1 - cur]) for launch shape L.
 template <typename R>
-RunArgs<R> run_args(const Mesh &m, Ctl *ctl, const Work<R> &w, int cur, int target_blocks);
+RunArgs<R> run_args(const Mesh &m, Ctl *ctl, const Work<R> &w, int cur, const Launch &L);
 // Field `which` of state w.s[cur] as doubles into `out`: 0 rho, 1 e, 2 p, 3 q
 // (cells), 4 u, 5 v, 6 w (nodes).
 template <typename R>

@@ -7,13 +7,12 @@
 namespace sale {
 namespace {
 
-// Tile shapes (columns per tile = 32 x CH) and the register cap (minimum
-// waves per SIMD) of the two z-marching kernels; tuned on MI355X.
-constexpr int CH = 16;
+// Register cap (minimum waves per SIMD) of the two z-marching kernels. Their
+// tile shape (32 x CH columns, one thread each) is a template parameter; the
+// launch shape picks CH per kernel at run time.
 #ifndef SALE_WAVES_STEP
 #define SALE_WAVES_STEP 4
 #endif
-static_assert(32 * CH == kStepThreads, "step kernels use 512-thread blocks");
 constexpr int TPB = 256;  // simple per-element kernels
 
 // ---------------------------------------------------------------------------------
@@ -23,16 +22,16 @@ __global__ void k_begin(Mesh m, Ctl *ctl) {
   if (threadIdx.x == 0 && blockIdx.x == 0) begin_step(m, ctl, 0x7fffffffffffffffll);
 }
 
-template <typename R>
-__global__ __launch_bounds__(kStepThreads, SALE_WAVES_STEP) void k_lagrange(RunArgs<R> a) {
+template <typename R, int CH>
+__global__ __launch_bounds__(32 * CH, SALE_WAVES_STEP) void k_lagrange(RunArgs<R> a) {
   __shared__ double lds[lagrange_lds_doubles<CH>()];
   if (a.ctl->done) return;
   const bool t = lagrange_tile<R, CH>(a, xcd_logical_block(blockIdx.x, gridDim.x), a.ctl->dt, lds);
   if (t) atomicOr(&a.ctl->status, SALE_FLAG_TANGLE);
 }
 
-template <typename R>
-__global__ __launch_bounds__(kStepThreads, SALE_WAVES_STEP) void k_remap(RunArgs<R> a) {
+template <typename R, int CH>
+__global__ __launch_bounds__(32 * CH, SALE_WAVES_STEP) void k_remap(RunArgs<R> a) {
   __shared__ double lds[remap_lds_doubles<CH>()];
   const int b = xcd_logical_block(blockIdx.x, gridDim.x);
   if (a.ctl->done) {
@@ -42,7 +41,7 @@ __global__ __launch_bounds__(kStepThreads, SALE_WAVES_STEP) void k_remap(RunArgs
   double amax;
   bool bad;
   remap_tile<R, CH>(a, b, lds, &amax, &bad);
-  block_max_to_ctl<kStepThreads>(a.ctl, amax, bad);
+  block_max_to_ctl<32 * CH>(a.ctl, amax, bad);
 }
 
 // ---------------------------------------------------------------------------------
@@ -284,11 +283,16 @@ Grid2 make_grid(int nx, int ny, int nplanes, int tile_x, int tile_y, int target_
 
 }  // namespace
 
-Grid2 grid_lagrange(const Mesh &m, int target_blocks) {
-  return make_grid(m.nx, m.ny, m.nz, 32 - 3, CH - 3, target_blocks);
+Grid2 grid_lagrange(const Mesh &m, int target_blocks, int rows) {
+  return make_grid(m.nx, m.ny, m.nz, 32 - 3, rows - 3, target_blocks);
 }
-Grid2 grid_remap(const Mesh &m, int target_blocks) {
-  return make_grid(m.nx, m.ny, m.nz, 32 - 4, CH - 4, target_blocks);
+Grid2 grid_remap(const Mesh &m, int target_blocks, int rows) {
+  return make_grid(m.nx, m.ny, m.nz, 32 - 4, rows - 4, target_blocks);
+}
+
+bool launch_valid(const Launch &L) {
+  auto ok = [](int r) { return r == 8 || r == 16 || r == 32; };
+  return ok(L.rows_a) && ok(L.rows_b) && L.target >= 1 && L.target <= (1 << 20);
 }
 
 // ---- workspace layout -----------------------------------------------------------------
@@ -392,7 +396,7 @@ hipError_t launch_set_t_end(Ctl *ctl, double t_end, hipStream_t s) {
 }
 
 template <typename R>
-RunArgs<R> run_args(const Mesh &m, Ctl *ctl, const Work<R> &w, int cur, int target_blocks) {
+RunArgs<R> run_args(const Mesh &m, Ctl *ctl, const Work<R> &w, int cur, const Launch &L) {
   RunArgs<R> a;
   a.m = m;
   a.ctl = ctl;
@@ -402,21 +406,40 @@ RunArgs<R> run_args(const Mesh &m, Ctl *ctl, const Work<R> &w, int cur, int targ
   a.vp = w.vp;
   a.wp = w.wp;
   a.geo = w.geo;
-  a.ga = grid_lagrange(m, target_blocks);
-  a.gb = grid_remap(m, target_blocks);
+  a.ga = grid_lagrange(m, L.target, L.rows_a);
+  a.gb = grid_remap(m, L.target, L.rows_b);
   return a;
 }
 
+template <typename R, int CH>
+void launch_lagrange(const RunArgs<R> &a, hipStream_t s) {
+  hipLaunchKernelGGL((k_lagrange<R, CH>), dim3(a.ga.blocks()), dim3(32 * CH), 0, s, a);
+}
+template <typename R, int CH>
+void launch_remap(const RunArgs<R> &a, hipStream_t s) {
+  hipLaunchKernelGGL((k_remap<R, CH>), dim3(a.gb.blocks()), dim3(32 * CH), 0, s, a);
+}
+
 template <typename R>
-hipError_t launch_step(const Mesh &m, Ctl *ctl, const Work<R> &w, int cur, hipStream_t s, const hipEvent_t *ev) {
-  const RunArgs<R> a = run_args<R>(m, ctl, w, cur, 3072);
+hipError_t launch_step(const Mesh &m, Ctl *ctl, const Work<R> &w, int cur, const Launch &L, hipStream_t s,
+                       const hipEvent_t *ev) {
+  if (!launch_valid(L)) return hipErrorInvalidValue;
+  const RunArgs<R> a = run_args<R>(m, ctl, w, cur, L);
   hipError_t e = hipSuccess;
   if (ev) e = hipEventRecord(ev[0], s);
   hipLaunchKernelGGL(k_begin, dim3(1), dim3(64), 0, s, m, ctl);
   if (ev && e == hipSuccess) e = hipEventRecord(ev[1], s);
-  hipLaunchKernelGGL(k_lagrange<R>, dim3(a.ga.blocks()), dim3(kStepThreads), 0, s, a);
+  switch (L.rows_a) {
+    case 8: launch_lagrange<R, 8>(a, s); break;
+    case 32: launch_lagrange<R, 32>(a, s); break;
+    default: launch_lagrange<R, 16>(a, s); break;
+  }
   if (ev && e == hipSuccess) e = hipEventRecord(ev[2], s);
-  hipLaunchKernelGGL(k_remap<R>, dim3(a.gb.blocks()), dim3(kStepThreads), 0, s, a);
+  switch (L.rows_b) {
+    case 8: launch_remap<R, 8>(a, s); break;
+    case 32: launch_remap<R, 32>(a, s); break;
+    default: launch_remap<R, 16>(a, s); break;
+  }
   if (ev && e == hipSuccess) e = hipEventRecord(ev[3], s);
   const hipError_t l = hipGetLastError();
   return l != hipSuccess ? l : e;
@@ -445,8 +468,8 @@ hipError_t launch_export(const Mesh &m, const Work<R> &w, int cur, int which, do
                                            long long, double, hipStream_t);                              \
   template hipError_t launch_init_user<R>(const Mesh &, Ctl *, const Work<R> &, const double *const[5],  \
                                           bool, double, long long, double, hipStream_t);                 \
-  template RunArgs<R> run_args<R>(const Mesh &, Ctl *, const Work<R> &, int, int);                       \
-  template hipError_t launch_step<R>(const Mesh &, Ctl *, const Work<R> &, int, hipStream_t,                \
+  template RunArgs<R> run_args<R>(const Mesh &, Ctl *, const Work<R> &, int, const Launch &);            \
+  template hipError_t launch_step<R>(const Mesh &, Ctl *, const Work<R> &, int, const Launch &, hipStream_t, \
                                     const hipEvent_t *);                                                 \
   template hipError_t launch_totals<R>(const Mesh &, Ctl *, const Work<R> &, int, hipStream_t);          \
   template hipError_t launch_export<R>(const Mesh &, const Work<R> &, int, int, double *, hipStream_t);

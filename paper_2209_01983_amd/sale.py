@@ -37,7 +37,7 @@ NODE_FIELDS = ("u", "v", "w")
 
 # functions the header declares (checked by the tests against include/sale.h)
 EXPORTS = ("sale_workspace_bytes", "sale_init", "sale_step", "sale_run", "sale_fields",
-           "sale_step_timed", "sale_status", "sale_destroy", "sale_strerror")
+           "sale_step_timed", "sale_set_launch", "sale_status", "sale_destroy", "sale_strerror")
 POOL_EXPORTS = ("sale_pool_create", "sale_pool_admit", "sale_pool_advance", "sale_pool_poll",
                 "sale_pool_fields", "sale_pool_release", "sale_pool_destroy")
 
@@ -88,6 +88,8 @@ def lib():
         L.sale_fields.restype = C.c_int
         L.sale_step_timed.argtypes = [C.c_void_p, C.c_int32, C.POINTER(C.c_float)]
         L.sale_step_timed.restype = C.c_int
+        L.sale_set_launch.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_int32]
+        L.sale_set_launch.restype = C.c_int
         L.sale_status.argtypes = [C.c_void_p, C.POINTER(C.c_int32)]
         L.sale_status.restype = C.c_int
         L.sale_destroy.argtypes = [C.c_void_p]
@@ -149,6 +151,10 @@ def sale_step_timed(ctx, n: int):
     ms = (C.c_float * 3)()
     rc = lib().sale_step_timed(ctx, n, ms)
     return rc, [float(x) for x in ms]
+
+
+def sale_set_launch(ctx, rows_lagrange: int, rows_remap: int, target_blocks: int) -> int:
+    return lib().sale_set_launch(ctx, rows_lagrange, rows_remap, target_blocks)
 
 
 def sale_status(ctx):
@@ -309,6 +315,11 @@ class SaleRun:
         if rc != SALE_OK:
             raise SaleError(rc, "sale_step_timed")
         return ms
+
+    def set_launch(self, rows_lagrange=16, rows_remap=16, target_blocks=3072):
+        rc = sale_set_launch(self.ctx, rows_lagrange, rows_remap, target_blocks)
+        if rc != SALE_OK:
+            raise SaleError(rc, "sale_set_launch")
 
     def run(self, t_end=-1.0, max_steps=1 << 40) -> int:
         return sale_run(self.ctx, t_end, max_steps)

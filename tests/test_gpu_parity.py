@@ -391,3 +391,53 @@ def test_graph_replays_are_bitwise_the_eager_steps(precision):
     hf = h.fields()
     for k in FIELDS:
         assert np.array_equal(hf[k], mid[k]), k
+
+
+# ---------------------------------------------------------------------------
+# launch shapes and the autotuner
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("precision", [sale.SALE_FP64, sale.SALE_MIXED32])
+def test_every_launch_shape_gives_the_same_bits(precision):
+    n = (70, 37, 23)
+    say("launch shapes", n, precision)
+    cfg = sale.make_config(*n, hi=(1.0, 0.8, 1.3), t_end=100.0, precision=precision)
+    st = random_state(*n, seed=21)
+    ref = None
+    for ra, rb, t in ((16, 16, 3072), (8, 8, 3072), (32, 32, 3072), (8, 32, 64), (32, 8, 100000), (16, 32, 1)):
+        r = user_run(cfg, st)
+        r.set_launch(ra, rb, t)
+        r.step(4)
+        f = r.fields()
+        if ref is None:
+            ref = f
+            if precision == sale.SALE_FP64:
+                s = oracle_state(st)
+                o = orc.Oracle(grid_of(cfg))
+                for _ in range(4):
+                    assert o.step(s)[0] == orc.OK
+                assert_parity(f, s, what="default shape")
+        else:
+            for k in FIELDS:
+                assert np.array_equal(f[k], ref[k]), (ra, rb, t, k)
+    r = user_run(cfg, st)
+    for bad in ((12, 16, 3072), (16, 64, 3072), (16, 16, 0)):
+        assert sale.sale_set_launch(r.ctx, *bad) == sale.SALE_EINVAL
+
+
+def test_autotuner_picks_a_shape_and_caches_it(tmp_path):
+    from paper_2209_01983_amd import tune
+    cfg = sale.make_config(48, 48, 48, hi=(1.2, 1.2, 1.2), t_end=1.0)
+    path = str(tmp_path / "launch.json")
+    best = tune.tune(cfg, steps=2, warmup=1, targets=(1024, 3072), path=path)
+    say("tuned", {k: v for k, v in best.items() if k != "candidates"})
+    assert best["rows_a"] in tune.ROWS and best["rows_b"] in tune.ROWS and best["target"] in (1024, 3072)
+    assert len(best["candidates"]) == 6
+    r = sale.SaleRun(cfg, sale.sedov_problem())
+    assert tune.apply(r, path=path) == {"rows_a": best["rows_a"], "rows_b": best["rows_b"],
+                                        "target": best["target"]}
+    r.step(3)
+    q = sale.SaleRun(cfg, sale.sedov_problem())
+    q.step(3)
+    a, b = r.fields(), q.fields()
+    for k in FIELDS:
+        assert np.array_equal(a[k], b[k]), k

@@ -109,3 +109,22 @@ def test_request_geometry_follows_the_stated_setup():
     cfg, prob = workloads.request_problem({"kind": "sedov", "n": (20, 40, 30), "edep": 0.3}, sale.SALE_FP64)
     assert tuple(cfg.hi) == pytest.approx((0.6, 1.2, 0.9))
     assert list(prob.sedov) == pytest.approx([1.0, 1e-6, 0.3])
+
+
+def test_tuner_choice_and_cache_round_trip(tmp_path, monkeypatch):
+    from paper_2209_01983_amd import tune
+    times = {(8, 1024): (3.0, 2.0), (16, 1024): (1.0, 2.5), (32, 1024): (1.5, 1.8),
+             (8, 2048): (2.0, 1.0), (16, 2048): (1.2, 1.1), (32, 2048): (1.4, 1.3)}
+    best = tune.choose(times)
+    # target 1024: 1.0 + 1.8 = 2.8; target 2048: 1.2 + 1.0 = 2.2
+    assert (best["rows_a"], best["rows_b"], best["target"]) == (16, 8, 2048)
+    assert best["ms"] == pytest.approx(2.2)
+    path = str(tmp_path / "c.json")
+    cfg = sale.make_config(20, 30, 40, precision=sale.SALE_MIXED32)
+    monkeypatch.setattr(tune, "arch", lambda: "gfx950")
+    cache = {tune.key("gfx950", "lagrange", cfg): {"rows": 32, "target": 6144, "ms": 1.0},
+             tune.key("gfx950", "remap", cfg): {"rows": 8, "target": 6144, "ms": 1.0}}
+    tune.save_cache(cache, path)
+    assert tune.lookup(cfg, path) == {"rows_a": 32, "rows_b": 8, "target": 6144}
+    assert tune.key("gfx950", "remap", cfg) == "gfx950|remap|20x30x40|mixed32"
+    assert tune.lookup(sale.make_config(20, 30, 41), path) is None
