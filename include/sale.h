@@ -8,7 +8,7 @@
  * "Advection" kernels of the ScalSALE framework (arXiv 2209.01983, Sec. I-D
  * and Table I), for a single ideal gas, p = (gamma-1) rho e (Sec. I-C/I-D),
  * with cell-centred density and internal energy and vertex velocities
- * (cell and vertex quantities, Sec. III-B/III-C). The paper prints no scheme
+ * (cell and vertex quantities, Sec. III-C/III-D). The paper prints no scheme
  * equations; the library computes the scheme fixed by the project's FP64
  * oracle: acoustic half-step pressure predictor, von Neumann-Richtmyer +
  * Landshoff viscosity, compatible energy, exact trilinear swept volumes,

@@ -11,7 +11,7 @@
  *   - a SALE hydro scheme with a Lagrangian kernel, an Eulerian rezone and an
  *     advection phase on a structured grid (Sec. I-D, Table I);
  *   - the ideal-gas equation of state (Sec. I-C/I-D);
- *   - vertex quantities beside cell quantities (Sec. III-B/III-C);
+ *   - vertex quantities beside cell quantities (Sec. III-C/III-D);
  *   - density computed in the hydro module (Sec. III-A);
  *   - Sod and Sedov-Taylor as verification flows (Sec. I-D, Fig. 2).
  * The paper prints no equations for the scheme. Every formula below is the

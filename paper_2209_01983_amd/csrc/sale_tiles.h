@@ -5,7 +5,7 @@
 // Eulerian rezone and donor-cell advection back to the fixed mesh (ScalSALE
 // Sec. I-D and Table I: "Lagrangian rezoning", "Eulerian rezoning",
 // "Advection"), with the ideal-gas EoS (Sec. I-C/I-D), cell-centred rho/e/p/q
-// and vertex velocities (Sec. III-B/III-C) and density as mass over volume
+// and vertex velocities (Sec. III-C/III-D) and density as mass over volume
 // (Sec. III-A). The paper prints no scheme equations; the tiles compute the
 // scheme of the project's FP64 oracle (its steps O1..O12):
 //
