@@ -88,7 +88,10 @@ extern "C" {
 
 /* ---- configuration ----------------------------------------------------- */
 typedef struct {
-  int32_t nx, ny, nz;       /* cells per axis, >= 1                         */
+  int32_t nx, ny, nz;       /* cells per axis, >= 1; (nx+1)(ny+1)(nz+1) * 8
+                               must stay below 2^32 bytes (each field array
+                               is addressed with 32-bit offsets), e.g. up
+                               to 811^3 cells                              */
   double lo[3], hi[3];      /* box; cell size (hi-lo)/n per axis, hi > lo   */
   double gamma;             /* ideal-gas ratio of specific heats, > 1       */
   double cfl;               /* Courant number, 0 < cfl < 1 (default 0.5)    */

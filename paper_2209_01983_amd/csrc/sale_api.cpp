@@ -70,8 +70,9 @@ int validate_config(const sale_config *c) {
   if (c->precision != SALE_FP64 && c->precision != SALE_MIXED32) return SALE_EINVAL;
   for (int a = 0; a < 6; a++)
     if (c->bc[a] != SALE_BC_REFLECT) return SALE_EINVAL;
-  const int64_t ncell = (int64_t)c->nx * c->ny * c->nz;
-  if (ncell > ((int64_t)1 << 34)) return SALE_EINVAL;
+  // the step kernels address each field array with 32-bit byte offsets
+  const int64_t nnode = (int64_t)(c->nx + 1) * (c->ny + 1) * (c->nz + 1);
+  if (nnode * (int64_t)sizeof(double) >= ((int64_t)1 << 32)) return SALE_EINVAL;
   return SALE_OK;
 }
 
@@ -85,6 +86,7 @@ Mesh make_mesh(const sale_config *c) {
   m.dy = (c->hi[1] - c->lo[1]) / (double)c->ny;
   m.dz = (c->hi[2] - c->lo[2]) / (double)c->nz;
   m.V0 = m.dx * m.dy * m.dz;
+  m.iV0 = 1.0 / m.V0;
   m.h = fmin(m.dx, fmin(m.dy, m.dz));
   m.ax = m.dy * m.dz / 4.0;
   m.ay = m.dz * m.dx / 4.0;
@@ -93,6 +95,15 @@ Mesh make_mesh(const sale_config *c) {
   m.cfl = c->cfl;
   m.cq = c->c_quad;
   m.cl = c->c_lin;
+  m.gm1 = m.gamma - 1.0;
+  m.ggm1 = m.gamma * (m.gamma - 1.0);
+  m.cq4h = 4.0 * m.cq * m.h;
+  m.hyz = m.dy * m.dz;
+  m.hzx = m.dz * m.dx;
+  m.hxy = m.dx * m.dy;
+  m.hdx = 0.5 * m.dx;
+  m.hdy = 0.5 * m.dy;
+  m.hdz = 0.5 * m.dz;
   m.ncell = (int64_t)c->nx * c->ny * c->nz;
   m.nnode = (int64_t)(c->nx + 1) * (c->ny + 1) * (c->nz + 1);
   return m;

@@ -29,9 +29,10 @@ __device__ __forceinline__ bool cell_in(const Mesh &m, int i, int j, int k) {
 // The two middle brackets reduce to 1D integrals along the edges t = 0 and
 // s = 0 (their s t terms cancel) and the triple product integrates to
 // A.(B x C) + 1/2 A.((B - C) x E) + 1/4 C.(B x E).
+// h12 = h1 h2, hh1 = h1 / 2, hh2 = h2 / 2.
 template <typename R>
 __device__ __forceinline__ R swept_volume(const R d0[3], const R d1[3], const R d2[3], const R d3[3],
-                                          R h1, R h2) {
+                                          R h12, R hh1, R hh2) {
   R A[3], B[3], C[3], E[3];
 #pragma unroll
   for (int a = 0; a < 3; a++) {
@@ -41,7 +42,7 @@ __device__ __forceinline__ R swept_volume(const R d0[3], const R d1[3], const R 
     E[a] = (d3[a] - d1[a]) - C[a];
   }
   const R half = R(0.5), third = R(1) / R(3), quarter = R(0.25);
-  const R t0 = h1 * h2 * (quarter * ((d0[0] + d1[0]) + (d2[0] + d3[0])));
+  const R t0 = h12 * (quarter * ((d0[0] + d1[0]) + (d2[0] + d3[0])));
   const R i1 = (A[0] * C[2] + half * (A[0] * E[2] + B[0] * C[2]) + third * B[0] * E[2]) -
                (A[2] * C[0] + half * (A[2] * E[0] + B[2] * C[0]) + third * B[2] * E[0]);
   const R i2 = (A[0] * B[1] + half * (A[0] * E[1] + C[0] * B[1]) + third * C[0] * E[1]) -
@@ -52,7 +53,23 @@ __device__ __forceinline__ R swept_volume(const R d0[3], const R d1[3], const R 
   const R BE0 = B[1] * E[2] - B[2] * E[1], BE1 = B[2] * E[0] - B[0] * E[2], BE2 = B[0] * E[1] - B[1] * E[0];
   const R trip = (A[0] * BC0 + A[1] * BC1 + A[2] * BC2) + half * (A[0] * DE0 + A[1] * DE1 + A[2] * DE2) +
                  quarter * (C[0] * BE0 + C[1] * BE1 + C[2] * BE2);
-  return t0 + half * h1 * i1 + half * h2 * i2 + third * trip;
+  return t0 + hh1 * i1 + hh2 * i2 + third * trip;
+}
+
+// Cell divergence D = (1/V0) sum_p S_cp . u_p from the halves of its corner
+// sums on the cell's lower (a) and upper (b) node planes: x and y halves are
+// pairwise edge differences, z halves the sums of w over the plane's four
+// nodes. Written with explicit FMAs so that every kernel forming D of the
+// same state gets the same bits (a restart must reproduce a run exactly).
+template <typename R>
+__device__ __forceinline__ R divergence(const Mesh &m, R xa, R xb, R ya, R yb, R za, R zb) {
+  return fma(R(m.az), zb - za, fma(R(m.ay), ya + yb, R(m.ax) * (xa + xb))) * R(m.iV0);
+}
+
+// node speed |u|, same bits in every kernel
+template <typename R>
+__device__ __forceinline__ R speed(R u, R v, R w) {
+  return sqrt(fma(w, w, fma(v, v, u * u)));
 }
 
 template <typename R>

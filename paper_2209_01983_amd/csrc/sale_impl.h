@@ -14,9 +14,16 @@ struct Mesh {
   double lo[3];       // lower corner of the box
   double dx, dy, dz;  // cell edge lengths
   double V0;          // cell volume dx*dy*dz
+  double iV0;         // 1 / V0
   double h;           // min(dx, dy, dz): length scale of q and the CFL rule
   double ax, ay, az;  // quarter face areas dy*dz/4, dz*dx/4, dx*dy/4
   double gamma, cfl, cq, cl;
+  // products of constants, formed once on the host (device code would form
+  // them in vector registers and keep them live)
+  double gm1, ggm1;          // gamma - 1, gamma (gamma - 1)
+  double cq4h;               // 4 c_quad h
+  double hyz, hzx, hxy;      // face areas dy dz, dz dx, dx dy
+  double hdx, hdy, hdz;      // half spacings dx/2, dy/2, dz/2
   int64_t ncell, nnode;
 };
 

@@ -7,12 +7,19 @@
 namespace sale {
 namespace {
 
-// Register cap (minimum waves per SIMD) of the two z-marching kernels. Their
-// tile shape (32 x CH columns, one thread each) is a template parameter; the
-// launch shape picks CH per kernel at run time.
-#ifndef SALE_WAVES_STEP
-#define SALE_WAVES_STEP 4
+// The two z-marching kernels are templates on their tile shape (32 x CH
+// columns, one thread each); the launch shape picks CH per kernel at run time.
+// Each shape has a register cap (minimum waves per SIMD): a block of 32 x CH
+// threads puts CH / 8 waves on each SIMD, so the cap fixes how many blocks
+// share a CU. Register spills are to be avoided: their reloads wait for every
+// outstanding global load and store of the wave.
+#ifndef SALE_WAVES_16
+#define SALE_WAVES_16 4
 #endif
+template <int CH>
+constexpr int waves_of() {
+  return CH == 12 ? 3 : CH == 24 ? 3 : CH == 16 ? SALE_WAVES_16 : 4;
+}
 constexpr int TPB = 256;  // simple per-element kernels
 
 // ---------------------------------------------------------------------------------
@@ -23,7 +30,7 @@ __global__ void k_begin(Mesh m, Ctl *ctl) {
 }
 
 template <typename R, int CH>
-__global__ __launch_bounds__(32 * CH, SALE_WAVES_STEP) void k_lagrange(RunArgs<R> a) {
+__global__ __launch_bounds__(32 * CH, waves_of<CH>()) void k_lagrange(RunArgs<R> a) {
   __shared__ double lds[lagrange_lds_doubles<CH>()];
   if (a.ctl->done) return;
   const bool t = lagrange_tile<R, CH>(a, xcd_logical_block(blockIdx.x, gridDim.x), a.ctl->dt, lds);
@@ -31,7 +38,7 @@ __global__ __launch_bounds__(32 * CH, SALE_WAVES_STEP) void k_lagrange(RunArgs<R
 }
 
 template <typename R, int CH>
-__global__ __launch_bounds__(32 * CH, SALE_WAVES_STEP) void k_remap(RunArgs<R> a) {
+__global__ __launch_bounds__(32 * CH, waves_of<CH>()) void k_remap(RunArgs<R> a) {
   __shared__ double lds[remap_lds_doubles<CH>()];
   const int b = xcd_logical_block(blockIdx.x, gridDim.x);
   if (a.ctl->done) {
@@ -60,21 +67,18 @@ __device__ __forceinline__ void node_ijk(const Mesh &m, int64_t n, int &i, int &
   k = (int)(r / (m.ny + 1));
 }
 
-// sum_p S_{c,p} . u_p of cell (i,j,k), as edge differences, in R
+// divergence D of cell (i,j,k) of state s, formed as in the step kernels
 template <typename R>
-__device__ __forceinline__ R corner_div(const Mesh &m, const State<R> &s, int i, int j, int k) {
-  const int64_t sy = m.nx + 1, sz = (int64_t)(m.nx + 1) * (m.ny + 1);
-  const int64_t n0 = nidx(m, i, j, k);
-  R sx = 0, syy = 0, szz = 0;
+__device__ __forceinline__ R state_divergence(const Mesh &m, const State<R> &s, int i, int j, int k) {
+  R x[2], y[2], z[2];
 #pragma unroll
-  for (int t2 = 0; t2 < 2; t2++)
-#pragma unroll
-    for (int t1 = 0; t1 < 2; t1++) {
-      sx += s.u[n0 + 1 + t1 * sy + t2 * sz] - s.u[n0 + t1 * sy + t2 * sz];
-      syy += s.v[n0 + sy + t1 + t2 * sz] - s.v[n0 + t1 + t2 * sz];
-      szz += s.w[n0 + sz + t1 + t2 * sy] - s.w[n0 + t1 + t2 * sy];
-    }
-  return R(m.ax) * sx + R(m.ay) * syy + R(m.az) * szz;
+  for (int c = 0; c < 2; c++) {
+    auto at = [&](const R *f, int a, int b) { return f[nidx(m, i + a, j + b, k + c)]; };
+    x[c] = (at(s.u, 1, 0) - at(s.u, 0, 0)) + (at(s.u, 1, 1) - at(s.u, 0, 1));
+    y[c] = (at(s.v, 0, 1) - at(s.v, 0, 0)) + (at(s.v, 1, 1) - at(s.v, 1, 0));
+    z[c] = ((at(s.w, 0, 0) + at(s.w, 1, 0)) + at(s.w, 0, 1)) + at(s.w, 1, 1);
+  }
+  return divergence(m, x[0], x[1], y[0], y[1], z[0], z[1]);
 }
 
 template <typename R>
@@ -85,13 +89,13 @@ __global__ __launch_bounds__(TPB) void k_signal(Mesh m, Ctl *ctl, State<R> s) {
   if (c < m.ncell) {
     int i, j, k;
     cell_ijk(m, c, i, j, k);
-    const R D = corner_div(m, s, i, j, k) / R(m.V0);
+    const R D = state_divergence(m, s, i, j, k);
     R smax = 0;
     for (int cc = 0; cc < 2; cc++)
       for (int b = 0; b < 2; b++)
         for (int aa = 0; aa < 2; aa++) {
           const int64_t n = nidx(m, i + aa, j + b, k + cc);
-          const R sp = sqrt(s.u[n] * s.u[n] + s.v[n] * s.v[n] + s.w[n] * s.w[n]);
+          const R sp = speed(s.u[n], s.v[n], s.w[n]);
           if (!isfinite(sp)) bad = true;
           smax = fmax(smax, sp);
         }
@@ -254,7 +258,7 @@ __global__ __launch_bounds__(TPB) void k_export(Mesh m, State<R> s, int which, d
     cell_ijk(m, q, i, j, k);
     const R gm = R(m.gamma), h = R(m.h);
     const R cs = sqrt(gm * (gm - R(1)) * fmax(e, R(0)));
-    const R D = corner_div(m, s, i, j, k) / R(m.V0);
+    const R D = state_divergence(m, s, i, j, k);
     R qv = 0;
     if (D < R(0)) {
       const R hd = h * D;
@@ -291,7 +295,7 @@ Grid2 grid_remap(const Mesh &m, int target_blocks, int rows) {
 }
 
 bool launch_valid(const Launch &L) {
-  auto ok = [](int r) { return r == 8 || r == 16 || r == 32; };
+  auto ok = [](int r) { return r == 8 || r == 12 || r == 16 || r == 24 || r == 32; };
   return ok(L.rows_a) && ok(L.rows_b) && L.target >= 1 && L.target <= (1 << 20);
 }
 
@@ -431,12 +435,16 @@ hipError_t launch_step(const Mesh &m, Ctl *ctl, const Work<R> &w, int cur, const
   if (ev && e == hipSuccess) e = hipEventRecord(ev[1], s);
   switch (L.rows_a) {
     case 8: launch_lagrange<R, 8>(a, s); break;
+    case 12: launch_lagrange<R, 12>(a, s); break;
+    case 24: launch_lagrange<R, 24>(a, s); break;
     case 32: launch_lagrange<R, 32>(a, s); break;
     default: launch_lagrange<R, 16>(a, s); break;
   }
   if (ev && e == hipSuccess) e = hipEventRecord(ev[2], s);
   switch (L.rows_b) {
     case 8: launch_remap<R, 8>(a, s); break;
+    case 12: launch_remap<R, 12>(a, s); break;
+    case 24: launch_remap<R, 24>(a, s); break;
     case 32: launch_remap<R, 32>(a, s); break;
     default: launch_remap<R, 16>(a, s); break;
   }

@@ -30,17 +30,32 @@
 // computed in double, as are dt and the signal-speed reduction.
 #pragma once
 
+#include <type_traits>
+
 #include "sale_device.h"
 
 namespace sale {
 
+// Element of plane k of a plane-major array (`plane` elements per z plane) at
+// the in-plane byte offset `off`: the plane base is uniform (scalar
+// registers), the offset a 32-bit per-thread value, so a load or store needs
+// no per-thread 64-bit address arithmetic.
+template <typename T>
+__device__ __forceinline__ T &plane_at(T *base, int64_t plane, int k, uint32_t off) {
+  const uint32_t b = (uint32_t)(plane * (int64_t)k * (int64_t)sizeof(T)) + off;
+  return *reinterpret_cast<T *>(reinterpret_cast<
+      typename std::conditional<std::is_const<T>::value, const char, char>::type *>(base) + (uint64_t)b);
+}
+
 // ---- O5: acoustic predictor P* of one cell (O2, O4 folded in) ----------------
+// Divisions by a quantity used more than once go through one reciprocal
+// (rounding-level differences from the oracle's divisions).
 template <typename R>
-__device__ __forceinline__ R predict_ps(const Mesh &m, R rho, R e, R D, R dt, bool &tangle) {
-  const R V0 = R(m.V0), gm = R(m.gamma), h = R(m.h);
+__device__ __forceinline__ R predict_ps(const Mesh &m, R rho, R e, R D, R dt, bool &tangle, R &inv_mc) {
+  const R V0 = R(m.V0), h = R(m.h), gm1 = R(m.gm1);
   const R mc = rho * V0;
-  const R p = (gm - R(1)) * rho * e;
-  const R cs = sqrt(gm * (gm - R(1)) * fmax(e, R(0)));
+  const R p = gm1 * rho * e;
+  const R cs = sqrt(R(m.ggm1) * fmax(e, R(0)));
   R q = R(0);
   if (D < R(0)) {
     const R hd = h * D;
@@ -52,17 +67,17 @@ __device__ __forceinline__ R predict_ps(const Mesh &m, R rho, R e, R D, R dt, bo
     tangle = true;
     return R(0);
   }
+  inv_mc = R(1) / mc;
   const R rs = mc / Vs;
-  const R es = e - (p + q) * dVs / mc;
-  return (gm - R(1)) * rs * es + q;
+  const R es = e - (p + q) * dVs * inv_mc;
+  return gm1 * rs * es + q;
 }
 
 // ---- O3: signal speed from a cell's divergence, energy and node speeds --------
 template <typename R>
 __device__ __forceinline__ R signal_from(const Mesh &m, R D, R e, R smax) {
-  const R gm = R(m.gamma);
-  const R cs = sqrt(gm * (gm - R(1)) * fmax(e, R(0)));
-  return cs + smax + R(4) * R(m.cq) * R(m.h) * fmax(-D, R(0));
+  const R cs = sqrt(R(m.ggm1) * fmax(e, R(0)));
+  return fma(R(m.cq4h), fmax(-D, R(0)), cs + smax);
 }
 
 // O3 at the start of a step: dt from the largest signal speed of the current
@@ -142,6 +157,8 @@ __device__ bool lagrange_tile(const RunArgs<R> &a, int b, double dtd, double *ld
   const bool nodecol = ci >= 1 && cj >= 1 && inner;  // u' computed here
   const bool own_node = ncol && ci >= 1 && cj >= 1 && (ci <= TX || gi == m.nx) && (cj <= TY || gj == m.ny);
   const bool own_cell = ci >= 1 && cj >= 1 && ci <= TX && cj <= TY && gi < m.nx && gj < m.ny;
+  const int64_t cpl = (int64_t)m.nx * m.ny, npl = (int64_t)(m.nx + 1) * (m.ny + 1);
+  const uint32_t cix = ccol ? (uint32_t)(gi + m.nx * gj) : 0u, nix = ncol ? (uint32_t)(gi + (m.nx + 1) * gj) : 0u;
 
   // LDS: bulk planes as R, delta ring and swept volumes as double
   R(*sU)[CH][CW] = reinterpret_cast<R(*)[CH][CW]>(lds);                // [3]
@@ -168,15 +185,15 @@ __device__ bool lagrange_tile(const RunArgs<R> &a, int b, double dtd, double *ld
   auto fetch = [&](int k) {
     fu = fv = fw = frho = fe = R(0);
     if (ncol && k + 1 >= 0 && k + 1 <= m.nz) {
-      const int64_t n = nidx(m, gi, gj, k + 1);
-      fu = cur.u[n];
-      fv = cur.v[n];
-      fw = cur.w[n];
+      const uint32_t o = nix * (uint32_t)sizeof(R);
+      fu = plane_at<const R>(cur.u, npl, k + 1, o);
+      fv = plane_at<const R>(cur.v, npl, k + 1, o);
+      fw = plane_at<const R>(cur.w, npl, k + 1, o);
     }
     if (ccol && k >= 0 && k < m.nz) {
-      const int64_t c = cidx(m, gi, gj, k);
-      frho = cur.rho[c];
-      fe = cur.e[c];
+      const uint32_t o = cix * (uint32_t)sizeof(R);
+      frho = plane_at<const R>(cur.rho, cpl, k, o);
+      fe = plane_at<const R>(cur.e, cpl, k, o);
     }
   };
   fetch(Z0 - 2);
@@ -190,7 +207,7 @@ __device__ bool lagrange_tile(const RunArgs<R> &a, int b, double dtd, double *ld
     sU[2][cj][ci] = wn;
     __syncthreads();
     // ---- P2 ----
-    R ps = 0, mc = 0;
+    R ps = 0, mc = 0, imc = 0;
     {
       R qxu = 0, qyu = 0, qzu = 0;
       if (inner) {
@@ -200,9 +217,9 @@ __device__ bool lagrange_tile(const RunArgs<R> &a, int b, double dtd, double *ld
       }
       if (ccol && k >= 0 && k < m.nz) {
         mc = rho_k * V0;
-        const R D = ((ax * (pxu + qxu) + ay * (pyu + qyu)) + az * (qzu - pzu)) / V0;
+        const R D = divergence(m, pxu, qxu, pyu, qyu, pzu, qzu);
         bool t = false;
-        ps = predict_ps(m, rho_k, e_k, D, dt, t);
+        ps = predict_ps(m, rho_k, e_k, D, dt, t, imc);
         if (t && own_cell && k >= Z0 && k < Z1) tangle = true;
       }
       pxu = qxu;
@@ -224,17 +241,18 @@ __device__ bool lagrange_tile(const RunArgs<R> &a, int b, double dtd, double *ld
           // node k is the +z corner of the cells of plane k-1, the -z corner of plane k
           const R Fx = ax * (fx + gx), Fy = ay * (fy + gy), Fz = az * (fz - gz);
           const R mp = R(0.125) * (mk + gm);
-          R u1 = u0 + dt * Fx / mp;
-          R v1 = v0 + dt * Fy / mp;
-          R w1 = w0 + dt * Fz / mp;
+          const R dtm = dt / mp;
+          R u1 = u0 + dtm * Fx;
+          R v1 = v0 + dtm * Fy;
+          R w1 = w0 + dtm * Fz;
           if (gi == 0 || gi == m.nx) u1 = R(0);
           if (gj == 0 || gj == m.ny) v1 = R(0);
           if (k == 0 || k == m.nz) w1 = R(0);
           if (own_node && k >= Z0 && k < NZ1) {
-            const int64_t n = nidx(m, gi, gj, k);
-            a.up[n] = u1;
-            a.vp[n] = v1;
-            a.wp[n] = w1;
+            const uint32_t o = nix * (uint32_t)sizeof(R);
+            plane_at<R>(a.up, npl, k, o) = u1;
+            plane_at<R>(a.vp, npl, k, o) = v1;
+            plane_at<R>(a.wp, npl, k, o) = w1;
           }
           d0 = dtd * (0.5 * ((double)u0 + (double)u1));
           d1 = dtd * (0.5 * ((double)v0 + (double)v1));
@@ -279,7 +297,7 @@ __device__ bool lagrange_tile(const RunArgs<R> &a, int b, double dtd, double *ld
         const double d1[3] = {A[0][cj + 1][ci], A[1][cj + 1][ci], A[2][cj + 1][ci]};
         const double d2[3] = {B[0][cj][ci], B[1][cj][ci], B[2][cj][ci]};
         const double d3[3] = {B[0][cj + 1][ci], B[1][cj + 1][ci], B[2][cj + 1][ci]};
-        vx = swept_volume(d0, d1, d2, d3, m.dy, m.dz);
+        vx = swept_volume(d0, d1, d2, d3, m.hyz, m.hdy, m.hdz);
       }
       // y face at node row gj between cells gj-1, gj; corners (s: z, t: x); comps (y, z, x)
       if (plane_ok && ci >= 1 && ci <= TX && cj >= 1 && cj <= TY + 1 && gj >= 1 && gj <= m.ny - 1 && gi >= 0 &&
@@ -288,7 +306,7 @@ __device__ bool lagrange_tile(const RunArgs<R> &a, int b, double dtd, double *ld
         const double d1[3] = {B[1][cj][ci], B[2][cj][ci], B[0][cj][ci]};
         const double d2[3] = {A[1][cj][ci + 1], A[2][cj][ci + 1], A[0][cj][ci + 1]};
         const double d3[3] = {B[1][cj][ci + 1], B[2][cj][ci + 1], B[0][cj][ci + 1]};
-        vy = swept_volume(d0, d1, d2, d3, m.dz, m.dx);
+        vy = swept_volume(d0, d1, d2, d3, m.hzx, m.hdz, m.hdx);
       }
       // z face at node plane k between cells k-1, k; corners (s: x, t: y); comps (z, x, y)
       if (own_cell && k >= 1 && k <= m.nz - 1) {
@@ -296,7 +314,7 @@ __device__ bool lagrange_tile(const RunArgs<R> &a, int b, double dtd, double *ld
         const double d1[3] = {B[2][cj][ci + 1], B[0][cj][ci + 1], B[1][cj][ci + 1]};
         const double d2[3] = {B[2][cj + 1][ci], B[0][cj + 1][ci], B[1][cj + 1][ci]};
         const double d3[3] = {B[2][cj + 1][ci + 1], B[0][cj + 1][ci + 1], B[1][cj + 1][ci + 1]};
-        dvz_up = swept_volume(d0, d1, d2, d3, m.dx, m.dy);
+        dvz_up = swept_volume(d0, d1, d2, d3, m.hxy, m.hdx, m.hdy);
       }
       sVX[cj][ci] = vx;
       sVY[cj][ci] = vy;
@@ -311,12 +329,12 @@ __device__ bool lagrange_tile(const RunArgs<R> &a, int b, double dtd, double *ld
         tangle = true;
       else
         rl = (double)m1 / VL;
-      const int64_t c = cidx(m, gi, gj, cp);
-      a.geo.rl[c] = R(rl);
-      a.geo.el[c] = R((double)e1 - (double)ps1 * work / (double)m1);
-      a.geo.dvx[c] = sVX[cj][ci];
-      a.geo.dvy[c] = sVY[cj][ci];
-      a.geo.dvz[c] = dvz_lo;
+      const uint32_t oR = cix * (uint32_t)sizeof(R), oD = cix * 8u;
+      plane_at<R>(a.geo.rl, cpl, cp, oR) = R(rl);
+      plane_at<R>(a.geo.el, cpl, cp, oR) = R((double)e1 - (double)ps1 * work / (double)m1);
+      plane_at<double>(a.geo.dvx, cpl, cp, oD) = sVX[cj][ci];
+      plane_at<double>(a.geo.dvy, cpl, cp, oD) = sVY[cj][ci];
+      plane_at<double>(a.geo.dvz, cpl, cp, oD) = dvz_lo;
     }
     dvz_lo = dvz_up;
     ps1 = ps;
@@ -376,9 +394,11 @@ __device__ void remap_tile(const RunArgs<R> &a, int b, double *lds, double *amax
 
   const bool ccol = gi >= 0 && gi < m.nx && gj >= 0 && gj < m.ny;
   const bool ncol = gi >= 0 && gi <= m.nx && gj >= 0 && gj <= m.ny;
+  const int64_t cpl = (int64_t)m.nx * m.ny, npl = (int64_t)(m.nx + 1) * (m.ny + 1);
+  const uint32_t cix = ccol ? (uint32_t)(gi + m.nx * gj) : 0u, nix = ncol ? (uint32_t)(gi + (m.nx + 1) * gj) : 0u;
   const bool r1 = ci >= 1 && cj >= 1 && ci <= CW - 2 && cj <= CH - 2;  // cells and nodes [-1, T]
   const bool r2 = ci >= 2 && cj >= 2 && ci <= CW - 2 && cj <= CH - 2;  // nodes [0, T]
-  const R V0 = R(m.V0), ax = R(m.ax), ay = R(m.ay), az = R(m.az);
+  const R V0 = R(m.V0), iV0 = R(m.iV0);
 
   // column carries: values of cell plane c / node plane c unless noted
   R rho_c = 0, rl_c = 0, el_c = 0;  // old density, rho^L, e^L
@@ -400,19 +420,19 @@ __device__ void remap_tile(const RunArgs<R> &a, int b, double *lds, double *amax
     f_rl = f_el = f_rho = f_u = f_v = f_w = R(0);
     f_vx = f_vy = f_vz = 0.0;
     if (ccol && cp >= 0 && cp < m.nz) {
-      const int64_t q = cidx(m, gi, gj, cp);
-      f_rl = a.geo.rl[q];
-      f_el = a.geo.el[q];
-      f_vx = a.geo.dvx[q];
-      f_vy = a.geo.dvy[q];
-      f_vz = a.geo.dvz[q];
-      f_rho = a.cur.rho[q];
+      const uint32_t oR = cix * (uint32_t)sizeof(R), oD = cix * 8u;
+      f_rl = plane_at<const R>(a.geo.rl, cpl, cp, oR);
+      f_el = plane_at<const R>(a.geo.el, cpl, cp, oR);
+      f_vx = plane_at<const double>(a.geo.dvx, cpl, cp, oD);
+      f_vy = plane_at<const double>(a.geo.dvy, cpl, cp, oD);
+      f_vz = plane_at<const double>(a.geo.dvz, cpl, cp, oD);
+      f_rho = plane_at<const R>(a.cur.rho, cpl, cp, oR);
     }
     if (ncol && cp >= 0 && cp <= m.nz) {
-      const int64_t n = nidx(m, gi, gj, cp);
-      f_u = a.up[n];
-      f_v = a.vp[n];
-      f_w = a.wp[n];
+      const uint32_t o = nix * (uint32_t)sizeof(R);
+      f_u = plane_at<const R>(a.up, npl, cp, o);
+      f_v = plane_at<const R>(a.vp, npl, cp, o);
+      f_w = plane_at<const R>(a.wp, npl, cp, o);
     }
   };
   // the u' ring starts empty (node planes below Z0-2 only feed non-owned results)
@@ -481,14 +501,14 @@ __device__ void remap_tile(const RunArgs<R> &a, int b, double *lds, double *amax
         const R nete = nxe_c + (epz_n - epz_c);
         mo = rho_c * V0;
         M = mo - netm;
-        const R rn = rho_c - netm / V0;
+        const R rn = rho_c - netm * iV0;
         const bool mine = own_cell && c >= Z0 && c < Z1;
         if (!(M > R(0)) || !(rn > R(0)) || !isfinite(rn)) {
           if (mine) bad = true;
         } else {
           ep_c = el_c + (el_c * netm - nete) / M;
         }
-        if (mine) a.nxt.rho[cidx(m, gi, gj, c)] = rn;
+        if (mine) plane_at<R>(a.nxt.rho, cpl, c, cix * (uint32_t)sizeof(R)) = rn;
         sz = muz_c + muz_n;
       }
       RS(SX)[cj][ci] = sx;  // slots 0..3 (RL..VY) are dead since P2
@@ -538,7 +558,6 @@ __device__ void remap_tile(const RunArgs<R> &a, int b, double *lds, double *amax
     {
       R un = 0, vn = 0, wn = 0, sp = 0, dk = 0;
       if (r2 && ncol && c >= 0 && c <= m.nz) {
-        const int64_t n = nidx(m, gi, gj, c);
         R P0 = mp * uB, P1 = mp * vB, P2 = mp * wB;
         R K = R(0.5) * mp * (uB * uB + vB * vB + wB * wB);
         auto flow = [&](R phi, R ud, R vd, R wd, R sgn) {
@@ -586,19 +605,21 @@ __device__ void remap_tile(const RunArgs<R> &a, int b, double *lds, double *amax
         if (!(mn > R(0))) {
           if (mine) bad = true;
         } else {
-          un = P0 / mn;
-          vn = P1 / mn;
-          wn = P2 / mn;
+          const R imn = R(1) / mn;
+          un = P0 * imn;
+          vn = P1 * imn;
+          wn = P2 * imn;
           if (gi == 0 || gi == m.nx) un = R(0);
           if (gj == 0 || gj == m.ny) vn = R(0);
           if (c == 0 || c == m.nz) wn = R(0);
-          dk = (K - R(0.5) * mn * (un * un + vn * vn + wn * wn)) / mn;
-          sp = sqrt(un * un + vn * vn + wn * wn);
+          dk = (K - R(0.5) * mn * (un * un + vn * vn + wn * wn)) * imn;
+          sp = speed(un, vn, wn);
         }
         if (mine) {
-          a.nxt.u[n] = un;
-          a.nxt.v[n] = vn;
-          a.nxt.w[n] = wn;
+          const uint32_t o = nix * (uint32_t)sizeof(R);
+          plane_at<R>(a.nxt.u, npl, c, o) = un;
+          plane_at<R>(a.nxt.v, npl, c, o) = vn;
+          plane_at<R>(a.nxt.w, npl, c, o) = wn;
         }
       }
       RS(UN)[cj][ci] = un;
@@ -626,8 +647,8 @@ __device__ void remap_tile(const RunArgs<R> &a, int b, double *lds, double *amax
         const int cm = c - 1;
         if (own_cell && cm >= Z0 && cm < Z1) {
           const R en = ep_c1 + R(0.125) * (dks1 + dks);
-          a.nxt.e[cidx(m, gi, gj, cm)] = en;
-          const R D = ((ax * (xn1 + xn) + ay * (yn1 + yn)) + az * (zn - zn1)) / V0;
+          plane_at<R>(a.nxt.e, cpl, cm, cix * (uint32_t)sizeof(R)) = en;
+          const R D = divergence(m, xn1, xn, yn1, yn, zn1, zn);
           const R sa = signal_from(m, D, en, fmax(sm1, sm));
           if (!(en >= R(0)) || !isfinite(en) || !isfinite(sa))
             bad = true;

@@ -36,7 +36,7 @@ def test_struct_layout_matches_header_sizes():
 
 
 @pytest.mark.parametrize("bad", [
-    dict(nx=0), dict(ny=-1), dict(gamma=1.0), dict(cfl=0.0), dict(cfl=1.0), dict(c_quad=-1.0),
+    dict(nx=0), dict(ny=-1), dict(nx=812, ny=812, nz=812), dict(gamma=1.0), dict(cfl=0.0), dict(cfl=1.0), dict(c_quad=-1.0),
     dict(t_end=-1.0), dict(precision=7), dict(hi=(0.0, 1.0, 1.0)),
 ])
 def test_invalid_config_rejected(bad):

@@ -403,7 +403,8 @@ def test_every_launch_shape_gives_the_same_bits(precision):
     cfg = sale.make_config(*n, hi=(1.0, 0.8, 1.3), t_end=100.0, precision=precision)
     st = random_state(*n, seed=21)
     ref = None
-    for ra, rb, t in ((16, 16, 3072), (8, 8, 3072), (32, 32, 3072), (8, 32, 64), (32, 8, 100000), (16, 32, 1)):
+    for ra, rb, t in ((16, 16, 3072), (8, 8, 3072), (32, 32, 3072), (8, 32, 64), (32, 8, 100000), (16, 32, 1),
+                      (12, 24, 3072), (24, 12, 500)):
         r = user_run(cfg, st)
         r.set_launch(ra, rb, t)
         r.step(4)
@@ -420,7 +421,7 @@ def test_every_launch_shape_gives_the_same_bits(precision):
             for k in FIELDS:
                 assert np.array_equal(f[k], ref[k]), (ra, rb, t, k)
     r = user_run(cfg, st)
-    for bad in ((12, 16, 3072), (16, 64, 3072), (16, 16, 0)):
+    for bad in ((10, 16, 3072), (16, 64, 3072), (16, 16, 0)):
         assert sale.sale_set_launch(r.ctx, *bad) == sale.SALE_EINVAL
 
 
