@@ -60,6 +60,8 @@ def parse():
     ap.add_argument("--serve-requests", type=int, default=1000)
     ap.add_argument("--serve-budget-gb", type=float, default=64.0)
     ap.add_argument("--no-tune", action="store_true", help="default launch shape, no autotuning")
+    ap.add_argument("--precision-report", type=int, default=0, metavar="N",
+                    help="also run the N^3 Sedov to t = 1 in FP64 and MIXED32 and report per-field errors")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run one plain device copy of 2 GiB (reference for HBM counters)")
     return ap.parse_args()
@@ -250,6 +252,48 @@ def copy_calibration(nbytes=2 << 30):
     say("copy calibration", nbytes, "bytes")
 
 
+def precision_report(n):
+    """Sedov n^3 to t = 1.0 in FP64 and in MIXED32; per-field L1-relative
+    (sum |a - b| / sum |b|) and Linf-relative (max |a - b| / max |b|; the
+    velocity components against the largest speed component) errors of the
+    MIXED32 fields against the FP64 ones, run times and steps."""
+    import numpy as np
+    import torch
+    from paper_2209_01983_amd import sale
+
+    out = {"workload": f"sedov {n}^3 to t=1.0"}
+    fields = {}
+    for name, prec in (("fp64", sale.SALE_FP64), ("mixed32", sale.SALE_MIXED32)):
+        cfg = sale.make_config(n, n, n, hi=(1.2, 1.2, 1.2), t_end=1.0, precision=prec)
+        r = sale.SaleRun(cfg, sale.sedov_problem())
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        while True:  # in slices, with a progress line after each
+            rc = r.run(max_steps=2000)
+            t, steps, _, _ = r.state()
+            say(f"precision report {name}: t = {t:.4f} after {steps} steps, {time.perf_counter() - a:.1f} s")
+            if rc != sale.SALE_OK:
+                break
+        wall = time.perf_counter() - a
+        if rc != sale.SALE_DONE:
+            raise RuntimeError(f"{name} run ended with {rc}")
+        m, e = r.totals()
+        fields[name] = r.fields()
+        out[name] = {"steps": steps, "wall_s": wall, "cell_updates_per_s": n ** 3 * steps / wall,
+                     "mass": m, "energy": e}
+        r.close()
+    a, b = fields["mixed32"], fields["fp64"]
+    vs = max(np.abs(b[k]).max() for k in ("u", "v", "w"))
+    err = {}
+    for k in ("rho", "e", "u", "v", "w"):
+        d = np.abs(a[k] - b[k])
+        scale = vs if k in ("u", "v", "w") else np.abs(b[k]).max()
+        err[k] = {"l1_rel": float(d.sum() / max(np.abs(b[k]).sum(), 1e-300)),
+                  "linf_rel": float(d.max() / max(scale, 1e-300))}
+    out["mixed32_vs_fp64"] = err
+    return out
+
+
 def cpu_bench(n, steps):
     """The FP64 oracle on this host (all cores, OpenMP): one warm-up step,
     then `steps` timed steps of the same Sedov workload."""
@@ -332,6 +376,9 @@ def main():
         say("batched")
         out["batched"] = batched()
         out["serving"] = serving(a.serve_requests, a.serve_budget_gb)
+    if a.precision_report:
+        say("precision report", a.precision_report)
+        out["precision"] = precision_report(a.precision_report)
     if not a.no_cpu:
         say("cpu oracle")
         cps, threads, secs = cpu_bench(n, a.cpu_steps)
