@@ -61,7 +61,9 @@ extern "C" {
 #define SALE_FP64 0       /* every quantity in FP64                      */
 #define SALE_MIXED32 1    /* FP32 storage and bulk arithmetic; FP64 for
                              node displacements, swept volumes, volume
-                             differences, the CFL dt and the totals       */
+                             differences, the CFL dt and the totals (the
+                             swept volumes reach the remap's FP32 fluxes
+                             as FP32)                                     */
 #define SALE_BC_REFLECT 0 /* reflective (slip) wall                      */
 
 #define SALE_SOD_X 0          /* Sod tube along x                        */

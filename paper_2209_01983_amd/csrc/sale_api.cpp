@@ -536,8 +536,8 @@ sale::PoolRun<R> pool_image(const PoolSlot &sl, const Work<R> &w) {
   r.wp = w.wp;
   r.geo = w.geo;
   // one z segment per tile: the pool's parallelism comes from its many runs
-  r.ga = sale::grid_lagrange(sl.m, 1, 16);
-  r.gb = sale::grid_remap(sl.m, 1, 16);
+  r.ga = sale::grid_lagrange(sl.m, 1, sale::kPoolRows);
+  r.gb = sale::grid_remap(sl.m, 1, sale::kPoolRows);
   r.step0 = sl.step0;
   r.step_target = sl.step_target;
   return r;

@@ -62,11 +62,12 @@ struct State {
 // to the second: rho^L, e^L and the swept volumes of the cell's three lower
 // faces (x face at its lower x side, etc.; zero on the domain boundary). A
 // cell's upper face is its +axis neighbour's lower face, or a wall. Swept
-// volumes are FP64 in both precisions.
+// volumes are computed in FP64 in both precisions and handed over in the bulk
+// type R, the type the remap's fluxes use them in.
 template <typename R>
 struct Geo {
   R *rl, *el;
-  double *dvx, *dvy, *dvz;
+  R *dvx, *dvy, *dvz;
 };
 
 // Workspace of one run: two states (ping-pong), the Lagrangian end velocity
@@ -171,6 +172,12 @@ struct PoolQueue {
   unsigned int timeouts;    // waits that hit the time cap
   unsigned int abort;       // set by a timed-out wait: later waits give up at once
 };
+
+// Tile rows of the persistent kernel (its tiles are 32 x kPoolRows columns).
+#ifndef SALE_POOL_ROWS
+#define SALE_POOL_ROWS 16
+#endif
+constexpr int kPoolRows = SALE_POOL_ROWS;
 
 // Persistent multi-run advance: prepare (queue head, per-run counters, first
 // dt) and the persistent kernel over `blocks` blocks; tables on the device.

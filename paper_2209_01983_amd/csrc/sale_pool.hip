@@ -33,8 +33,8 @@ namespace sale {
 
 namespace {
 
-constexpr int CH = 16;
-constexpr int NT = kStepThreads;
+constexpr int CH = kPoolRows;
+constexpr int NT = 32 * CH;
 constexpr int LDS_DOUBLES =
     lagrange_lds_doubles<CH>() > remap_lds_doubles<CH>() ? lagrange_lds_doubles<CH>() : remap_lds_doubles<CH>();
 // Cap of one wait, in ticks of the 100 MHz constant clock. A wait normally
@@ -91,8 +91,9 @@ __device__ __forceinline__ int find_run(const int *pref, int n, int j) {
 }
 
 template <typename R>
-__global__ __launch_bounds__(NT, SALE_WAVES_POOL) void k_pool(PoolRun<R> *runs, const int *act, const int *prefA,
-                                             const int *prefB, PoolQueue *qh) {
+__global__ __launch_bounds__(NT, SALE_WAVES_POOL) void k_pool(const PoolRun<R> *__restrict__ runs, const int *__restrict__ act,
+                                             const int *__restrict__ prefA, const int *__restrict__ prefB,
+                                             PoolQueue *qh) {
   __shared__ double lds[LDS_DOUBLES];
   __shared__ unsigned long long s_item;
   __shared__ int s_go;

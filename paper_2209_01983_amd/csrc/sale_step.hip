@@ -305,17 +305,15 @@ static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 template <typename R>
 size_t workspace_bytes(const Mesh &m) {
   const size_t cR = align256((size_t)m.ncell * sizeof(R)), nR = align256((size_t)m.nnode * sizeof(R));
-  const size_t cD = align256((size_t)m.ncell * sizeof(double));
   const size_t sD = align256((size_t)(m.ncell > m.nnode ? m.ncell : m.nnode) * sizeof(double));
   // ctl | 2 states | u' | rho^L, e^L | 3 swept volumes | partials | scratch
-  return align256(sizeof(Ctl)) + 2 * (2 * cR + 3 * nR) + 3 * nR + 2 * cR + 3 * cD +
+  return align256(sizeof(Ctl)) + 2 * (2 * cR + 3 * nR) + 3 * nR + 2 * cR + 3 * cR +
          align256(3 * TOT_BLOCKS * sizeof(double)) + sD;
 }
 
 template <typename R>
 void layout(const Mesh &m, void *ws, Ctl **ctl, Work<R> *w) {
   const size_t cR = align256((size_t)m.ncell * sizeof(R)), nR = align256((size_t)m.nnode * sizeof(R));
-  const size_t cD = align256((size_t)m.ncell * sizeof(double));
   const size_t sD = align256((size_t)(m.ncell > m.nnode ? m.ncell : m.nnode) * sizeof(double));
   char *p = (char *)ws;
   *ctl = (Ctl *)p;
@@ -342,9 +340,9 @@ void layout(const Mesh &m, void *ws, Ctl **ctl, Work<R> *w) {
   w->wp = takeR(nR);
   w->geo.rl = takeR(cR);
   w->geo.el = takeR(cR);
-  w->geo.dvx = takeD(cD);
-  w->geo.dvy = takeD(cD);
-  w->geo.dvz = takeD(cD);
+  w->geo.dvx = takeR(cR);
+  w->geo.dvy = takeR(cR);
+  w->geo.dvz = takeR(cR);
   w->partial = takeD(align256(3 * TOT_BLOCKS * sizeof(double)));
   w->scratch = takeD(sD);
 }

@@ -329,12 +329,12 @@ __device__ bool lagrange_tile(const RunArgs<R> &a, int b, double dtd, double *ld
         tangle = true;
       else
         rl = (double)m1 / VL;
-      const uint32_t oR = cix * (uint32_t)sizeof(R), oD = cix * 8u;
+      const uint32_t oR = cix * (uint32_t)sizeof(R);
       plane_at<R>(a.geo.rl, cpl, cp, oR) = R(rl);
       plane_at<R>(a.geo.el, cpl, cp, oR) = R((double)e1 - (double)ps1 * work / (double)m1);
-      plane_at<double>(a.geo.dvx, cpl, cp, oD) = sVX[cj][ci];
-      plane_at<double>(a.geo.dvy, cpl, cp, oD) = sVY[cj][ci];
-      plane_at<double>(a.geo.dvz, cpl, cp, oD) = dvz_lo;
+      plane_at<R>(a.geo.dvx, cpl, cp, oR) = R(sVX[cj][ci]);
+      plane_at<R>(a.geo.dvy, cpl, cp, oR) = R(sVY[cj][ci]);
+      plane_at<R>(a.geo.dvz, cpl, cp, oR) = R(dvz_lo);
     }
     dvz_lo = dvz_up;
     ps1 = ps;
@@ -420,12 +420,12 @@ __device__ void remap_tile(const RunArgs<R> &a, int b, double *lds, double *amax
     f_rl = f_el = f_rho = f_u = f_v = f_w = R(0);
     f_vx = f_vy = f_vz = 0.0;
     if (ccol && cp >= 0 && cp < m.nz) {
-      const uint32_t oR = cix * (uint32_t)sizeof(R), oD = cix * 8u;
+      const uint32_t oR = cix * (uint32_t)sizeof(R);
       f_rl = plane_at<const R>(a.geo.rl, cpl, cp, oR);
       f_el = plane_at<const R>(a.geo.el, cpl, cp, oR);
-      f_vx = plane_at<const double>(a.geo.dvx, cpl, cp, oD);
-      f_vy = plane_at<const double>(a.geo.dvy, cpl, cp, oD);
-      f_vz = plane_at<const double>(a.geo.dvz, cpl, cp, oD);
+      f_vx = (double)plane_at<const R>(a.geo.dvx, cpl, cp, oR);
+      f_vy = (double)plane_at<const R>(a.geo.dvy, cpl, cp, oR);
+      f_vz = (double)plane_at<const R>(a.geo.dvz, cpl, cp, oR);
       f_rho = plane_at<const R>(a.cur.rho, cpl, cp, oR);
     }
     if (ncol && cp >= 0 && cp <= m.nz) {
