@@ -60,6 +60,9 @@ def parse():
     ap.add_argument("--serve-requests", type=int, default=1000)
     ap.add_argument("--serve-budget-gb", type=float, default=64.0)
     ap.add_argument("--no-tune", action="store_true", help="default launch shape, no autotuning")
+    ap.add_argument("--shape", default="", metavar="A,B,T",
+                    help="launch shape of the headline runs (tile rows of the two step kernels, z-split "
+                         "target); skips the autotuner")
     ap.add_argument("--precision-report", type=int, default=0, metavar="N",
                     help="also run the N^3 Sedov to t = 1 in FP64 and MIXED32 and report per-field errors")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -102,9 +105,10 @@ def kernel_source_digest():
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
+def measured_traffic(n, shape):
     """HBM bytes per step from the committed rocprofv3 counter summary, if it
-    was taken on the current kernel sources."""
+    was taken on the current kernel sources, at this mesh size and in this
+    launch shape."""
     if not os.path.exists(TRAFFIC_FILE):
         return None, "no counter summary"
     text = open(TRAFFIC_FILE).read()
@@ -114,11 +118,15 @@ def measured_traffic():
         return None, "counter summary unreadable"
     if m.group(1) != kernel_source_digest():
         return None, "kernels changed since the counters were taken"
+    w = re.search(r"counted on: (\d+)\^3, launch shape (\d+),(\d+),(\d+)", text)
+    if not w or int(w.group(1)) != n or tuple(int(x) for x in w.group(2, 3, 4)) != (
+            shape["rows_a"], shape["rows_b"], shape["target"]):
+        return None, "counters were taken at another size or launch shape"
     return float(b.group(1)), "rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated"
 
 
 # ---- workloads -----------------------------------------------------------------
-def headline(n, steps, warmup, precision, tuned=True):
+def headline(n, steps, warmup, precision, tuned=True, fixed=None):
     """(ms per step from HIP events around `steps` async steps, final t,
     per-kernel ms, launch shape). With `tuned`, the autotuner first picks the
     launch shape of the step kernels for this mesh and precision."""
@@ -127,7 +135,9 @@ def headline(n, steps, warmup, precision, tuned=True):
 
     cfg = sale.make_config(n, n, n, hi=(1.2, 1.2, 1.2), t_end=1.0, precision=precision)
     shape = {"rows_a": 16, "rows_b": 16, "target": 3072}
-    if tuned:
+    if fixed:
+        shape = dict(zip(("rows_a", "rows_b", "target"), fixed))
+    elif tuned:
         best = tune.tune(cfg, steps=4, warmup=1, save=False)
         shape = {k: best[k] for k in ("rows_a", "rows_b", "target")}
     run = sale.SaleRun(cfg, sale.sedov_problem())
@@ -324,16 +334,17 @@ def main():
         copy_calibration()
     n = a.n
     say("headline fp64", n)
-    ms, t_sim, k64, shape64 = headline(n, a.steps, a.warmup, sale.SALE_FP64, tuned=not a.no_tune)
+    fixed = tuple(int(x) for x in a.shape.split(",")) if a.shape else None
+    ms, t_sim, k64, shape64 = headline(n, a.steps, a.warmup, sale.SALE_FP64, tuned=not a.no_tune, fixed=fixed)
     say("headline mixed32", n)
-    ms32, _, k32, shape32 = headline(n, a.steps, a.warmup, sale.SALE_MIXED32, tuned=not a.no_tune)
+    ms32, _, k32, shape32 = headline(n, a.steps, a.warmup, sale.SALE_MIXED32, tuned=not a.no_tune, fixed=fixed)
     cells = n ** 3
     value = cells * 1e3 / ms
     abytes = algorithmic_bytes(n)
     step_kernel_ms = sum(k64)
     achieved = abytes / (step_kernel_ms * 1e-3) / 1e9
     comp = compulsory_bytes(n)
-    traffic, traffic_note = measured_traffic()
+    traffic, traffic_note = measured_traffic(n, shape64)
     kernels = []
     for name, kms in (("k_begin", k64[0]), ("k_lagrange", k64[1]), ("k_remap", k64[2])):
         b = comp.get(name)
