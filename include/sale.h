@@ -139,9 +139,10 @@ int sale_step(sale_ctx *ctx);
 
 /* Run until t >= t_end or until max_steps more steps were taken. t_end < 0
  * keeps the configured end time; otherwise it replaces it (the last step is
- * clipped to land on it). Steps are enqueued in chunks, mostly as replays of
- * a captured HIP graph of several steps (dt, t and the done decision stay in
- * device memory, so a replay past t_end is a no-op); the stream is
+ * clipped to land on it). Steps are enqueued in chunks -- once a context has
+ * run 128 steps through sale_run, mostly as replays of a captured HIP graph
+ * of several steps (dt, t and the done decision stay in device memory, so a
+ * replay past t_end is a no-op); the stream is
  * synchronised after each chunk to read the device status. Returns SALE_DONE
  * when t_end was reached, SALE_OK when max_steps ran out first,
  * SALE_ETANGLE / SALE_ENUMERIC on a flagged step. */
@@ -165,9 +166,11 @@ int sale_step_timed(sale_ctx *ctx, int32_t n, float ms[3]);
 
 /* Launch shape of the context's two step kernels (a tuning knob; results do
  * not depend on it): tiles of 32 x rows columns for the Lagrangian kernel and
- * the remap kernel (rows 8, 16 or 32; default 16 and 16), and the number of
- * blocks the split of the z extent into segments aims at (default 3072).
- * Synchronises the stream. SALE_EINVAL for other values. */
+ * the remap kernel (rows 8, 12, 16, 24 or 32; default 16 and 16), and the
+ * number of blocks the split of the z extent into segments aims at (0, the
+ * default: automatic -- a small mesh is split as finely as the chip holds its
+ * blocks at once, a large one aims at 3072 blocks). Synchronises the stream.
+ * SALE_EINVAL for other values. */
 int sale_set_launch(sale_ctx *ctx, int32_t rows_lagrange, int32_t rows_remap, int32_t target_blocks);
 
 /* Synchronise the stream and return the sticky status flags (SALE_FLAG_*).

@@ -33,6 +33,7 @@ struct sale_ctx {
   // on a private capture stream, replayed on `stream` by sale_run
   hipStream_t cap_stream = nullptr;
   hipGraphExec_t graph[2] = {nullptr, nullptr};
+  long long enqueued = 0;  // steps enqueued through sale_run
   ~sale_ctx() {
     for (int k = 0; k < 2; k++)
       if (graph[k]) (void)hipGraphExecDestroy(graph[k]);
@@ -41,8 +42,10 @@ struct sale_ctx {
 };
 
 // Steps per captured graph (even, so that a replay leaves the current state
-// in the buffer it started from).
+// in the buffer it started from), and the steps a context runs eagerly before
+// it captures one (a short run would not earn the capture back).
 constexpr int kGraphSteps = 8;
+constexpr long long kGraphAfter = 128;
 
 namespace sale_host {
 
@@ -214,9 +217,12 @@ hipError_t step_graph(sale_ctx *x, int par, hipGraphExec_t *out) {
   return hipSuccess;
 }
 
-// n steps on the context's stream: whole graphs, then single steps.
+// n steps on the context's stream: whole graphs, then single steps (only
+// single steps while the context is young).
 hipError_t enqueue_steps(sale_ctx *x, int64_t n) {
-  for (; n >= kGraphSteps; n -= kGraphSteps) {
+  const bool graphs = x->enqueued >= kGraphAfter;
+  x->enqueued += n;
+  for (; graphs && n >= kGraphSteps; n -= kGraphSteps) {
     hipGraphExec_t g;
     hipError_t e = step_graph(x, x->cur, &g);
     if (e == hipSuccess) e = hipGraphLaunch(g, x->stream);

@@ -107,7 +107,7 @@ struct RunArgs {
 struct Launch {
   int rows_a = 16;     // Lagrange + geometry kernel
   int rows_b = 16;     // remap kernel
-  int target = 3072;   // blocks per kernel the z split aims at
+  int target = 0;      // blocks per kernel the z split aims at (0: automatic)
 };
 bool launch_valid(const Launch &L);
 

@@ -271,15 +271,36 @@ __global__ __launch_bounds__(TPB) void k_export(Mesh m, State<R> s, int which, d
 inline unsigned blocks(int64_t n) { return (unsigned)((n + TPB - 1) / TPB); }
 
 // z segments so that tiles x segments fills the chip a few times over
-Grid2 make_grid(int nx, int ny, int nplanes, int tile_x, int tile_y, int target_blocks) {
+// Split of the z extent into segments. A block marches its segment plus
+// `warm` warm-up planes. target_blocks > 0: aim at that many blocks, with at
+// least 8 planes per segment. target_blocks == 0 (automatic): a mesh whose
+// blocks, at 8 planes per segment, all fit on the chip at once (`resident`)
+// is latency bound -- split it as finely as keeps the fewest block rounds
+// times the planes each block marches; a larger mesh aims at 3072 blocks.
+Grid2 make_grid(int nx, int ny, int nplanes, int tile_x, int tile_y, int target_blocks, int warm, int resident) {
   Grid2 g;
   g.tx = (nx + tile_x - 1) / tile_x;
   g.ty = (ny + tile_y - 1) / tile_y;
   const int tiles = g.tx * g.ty;
-  int nseg = (target_blocks + tiles / 2) / tiles;
-  const int maxseg = nplanes / 8 > 1 ? nplanes / 8 : 1;  // keep >= 8 planes per segment
-  if (nseg > maxseg) nseg = maxseg;
-  if (nseg < 1) nseg = 1;
+  const int maxseg = nplanes / 8 > 1 ? nplanes / 8 : 1;  // >= 8 planes per segment
+  int nseg;
+  if (target_blocks == 0 && (long long)tiles * maxseg <= resident) {
+    nseg = 1;
+    long long best = -1;
+    for (int s = 1; s <= nplanes; s++) {
+      const long long rounds = ((long long)tiles * s + resident - 1) / resident;
+      const long long cost = rounds * ((nplanes + s - 1) / s + warm);
+      if (best < 0 || cost < best) {
+        best = cost;
+        nseg = s;
+      }
+    }
+  } else {
+    const int target = target_blocks > 0 ? target_blocks : 3072;
+    nseg = (target + tiles / 2) / tiles;
+    if (nseg > maxseg) nseg = maxseg;
+    if (nseg < 1) nseg = 1;
+  }
   g.seglen = (nplanes + nseg - 1) / nseg;
   g.nseg = (nplanes + g.seglen - 1) / g.seglen;
   return g;
@@ -287,16 +308,25 @@ Grid2 make_grid(int nx, int ny, int nplanes, int tile_x, int tile_y, int target_
 
 }  // namespace
 
+// blocks of a step kernel resident on MI355X at once (256 CUs), by tile rows
+static int resident_blocks(int rows) {
+  switch (rows) {
+    case 8: return 4 * 256;
+    case 12:
+    case 16: return 2 * 256;
+    default: return 256;
+  }
+}
 Grid2 grid_lagrange(const Mesh &m, int target_blocks, int rows) {
-  return make_grid(m.nx, m.ny, m.nz, 32 - 3, rows - 3, target_blocks);
+  return make_grid(m.nx, m.ny, m.nz, 32 - 3, rows - 3, target_blocks, 3, resident_blocks(rows));
 }
 Grid2 grid_remap(const Mesh &m, int target_blocks, int rows) {
-  return make_grid(m.nx, m.ny, m.nz, 32 - 4, rows - 4, target_blocks);
+  return make_grid(m.nx, m.ny, m.nz, 32 - 4, rows - 4, target_blocks, 4, resident_blocks(rows));
 }
 
 bool launch_valid(const Launch &L) {
   auto ok = [](int r) { return r == 8 || r == 12 || r == 16 || r == 24 || r == 32; };
-  return ok(L.rows_a) && ok(L.rows_b) && L.target >= 1 && L.target <= (1 << 20);
+  return ok(L.rows_a) && ok(L.rows_b) && L.target >= 0 && L.target <= (1 << 20);
 }
 
 // ---- workspace layout -----------------------------------------------------------------

@@ -15,7 +15,7 @@ import os
 from . import sale
 
 ROWS = (8, 16, 32)
-TARGETS = (1024, 2048, 3072, 6144, 12288)
+TARGETS = (0, 1024, 2048, 3072, 6144, 12288)  # 0: the library's automatic split
 KERNELS = ("lagrange", "remap")
 
 
