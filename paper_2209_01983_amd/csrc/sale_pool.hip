@@ -15,9 +15,10 @@
 // earliest unfinished item can always progress: the waits end. They are also
 // capped in time; a wait that hits the cap aborts the advance (every later
 // wait gives up at once, the runs concerned are flagged) so that every wave
-// exits soon. Writes of a finished tile are released at agent scope before the
-// counter moves and acquired by the waiting block after it sees the counter,
-// which covers the per-XCD L2 caches.
+// exits soon. Writes of a finished tile are released at agent scope (an L2
+// write-back, no invalidation) before the counter moves and acquired at agent
+// scope by the waiting block after it sees the counter, which covers the
+// per-XCD L2 caches.
 //
 // A run's current state buffer follows its own step count, so a run that is
 // done (step target or t_end reached, or flagged) simply skips its items.
@@ -133,7 +134,7 @@ __global__ __launch_bounds__(NT, SALE_WAVES_POOL) void k_pool(const PoolRun<R> *
           break;
         }
       }
-      __atomic_thread_fence(__ATOMIC_ACQUIRE);  // see the previous phase's writes
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // see the previous phase's writes
       // a run whose item could not wait is flagged: its state is not trusted
       if (!go) atomicOr(&ctl->status, SALE_FLAG_NUMERIC);
       s_go = go;
@@ -154,18 +155,18 @@ __global__ __launch_bounds__(NT, SALE_WAVES_POOL) void k_pool(const PoolRun<R> *
     }
     // finish the item: release its writes, count it; the last tile of the
     // phase opens the next phase (after a remap phase: the next time step)
-    __threadfence();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     __syncthreads();
     if (threadIdx.x == 0) {
       const unsigned int ntiles = (unsigned)(remap ? p.gb.blocks() : p.ga.blocks());
       const unsigned int old = atomicAdd(&ctl->tiles_done, 1u);
       if (old == ntiles - 1u) {
-        __atomic_thread_fence(__ATOMIC_ACQUIRE);
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         atomicExch(&ctl->tiles_done, 0u);
         if (remap && ran) ctl->clk_last = wall_clock64();  // the step just completed
         // the next advance's prepare starts the step after the last round
         if (remap && round + 1 < rounds) begin_step(p.m, ctl, p.step_target);
-        __threadfence();
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         atomicAdd(&ctl->phase, 1u);
       }
     }
