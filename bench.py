@@ -119,8 +119,10 @@ def measured_traffic(n, shape):
     if m.group(1) != kernel_source_digest():
         return None, "kernels changed since the counters were taken"
     w = re.search(r"counted on: (\d+)\^3, launch shape (\d+),(\d+),(\d+)", text)
-    if not w or int(w.group(1)) != n or tuple(int(x) for x in w.group(2, 3, 4)) != (
-            shape["rows_a"], shape["rows_b"], shape["target"]):
+    # z-split target 0 (automatic) splits a mesh this large like the target 3072
+    same_split = {int(w.group(4)), shape["target"]} <= {0, 3072} if w else False
+    if not w or int(w.group(1)) != n or (int(w.group(2)), int(w.group(3))) != (shape["rows_a"], shape["rows_b"]) \
+            or not (int(w.group(4)) == shape["target"] or (n >= 128 and same_split)):
         return None, "counters were taken at another size or launch shape"
     return float(b.group(1)), "rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated"
 

@@ -444,3 +444,18 @@ def test_autotuner_picks_a_shape_and_caches_it(tmp_path):
     a, b = r.fields(), q.fields()
     for k in FIELDS:
         assert np.array_equal(a[k], b[k]), k
+
+
+def test_step_timed_advances_like_steps_and_times_each_kernel():
+    say("step_timed")
+    cfg = sedov_cfg(48, t_end=10.0)
+    a = sale.SaleRun(cfg, sale.sedov_problem())
+    ms = a.step_timed(7)
+    assert len(ms) == 3 and all(x > 0.0 for x in ms), ms
+    b = sale.SaleRun(cfg, sale.sedov_problem())
+    b.step(7)
+    assert a.state() == b.state() and a.state()[1] == 7
+    fa, fb = a.fields(), b.fields()
+    for k in FIELDS:
+        assert np.array_equal(fa[k], fb[k]), k
+    assert sale.sale_step_timed(a.ctx, 0)[0] == sale.SALE_EINVAL
