@@ -67,6 +67,38 @@ def _corner_dot(X, Y, Z, dx, dy, dz):
     return dy * dz / 4 * sx + dz * dx / 4 * sy + dx * dy / 4 * sz
 
 
+def _vanleer(am, ap):
+    """harmonic slope limiter, zero unless the one-sided slopes share a sign"""
+    prod = am * ap
+    den = np.where(prod > 0, am + ap, 1.0)
+    return np.where(prod > 0, 2.0 * prod / den, 0.0)
+
+
+def _limited_slopes(q, ax, h):
+    """limited slope of q along array axis ax; zero at the first and last
+    entry along that axis (a wall on that side)"""
+    d = np.diff(q, axis=ax) / h
+    out = np.zeros_like(q)
+    n = q.shape[ax]
+    if n >= 3:
+        mid = [slice(None)] * 3
+        mid[ax] = slice(1, n - 1)
+        a = [slice(None)] * 3
+        a[ax] = slice(0, n - 2)
+        b = [slice(None)] * 3
+        b[ax] = slice(1, n - 1)
+        out[tuple(mid)] = _vanleer(d[tuple(a)], d[tuple(b)])
+    return out
+
+
+def _face_value(q_lo, s_lo, q_hi, s_hi, dv, area, h):
+    """second-order donor value of faces with swept volume dv between the
+    lower and upper neighbours: the limited linear profile of the donor at
+    the centroid of the swept slab"""
+    off = 0.5 * (h - np.abs(dv) / area)
+    return np.where(dv > 0, q_lo + s_lo * off, q_hi - s_hi * off)
+
+
 def _zero_walls(u, v, w):
     u[:, :, 0] = 0.0
     u[:, :, -1] = 0.0
@@ -131,26 +163,42 @@ def step(grid, rho, e, u, v, w, t):
     if np.any(VL <= 0):
         raise FloatingPointError("tangled cell")
     rhoL = m / VL
-    # donor-cell face fluxes
+    # donor-cell face fluxes (order 2: donor values from limited linear profiles)
+    o2 = getattr(grid, "order", 1) == 2
     mux = np.zeros_like(dvx)
     exf = np.zeros_like(dvx)
     f = dvx[:, :, 1:nx]
-    dr = np.where(f > 0, rhoL[:, :, :-1], rhoL[:, :, 1:])
-    de = np.where(f > 0, eL[:, :, :-1], eL[:, :, 1:])
+    if o2:
+        sr, se = _limited_slopes(rhoL, 2, dx), _limited_slopes(eL, 2, dx)
+        dr = _face_value(rhoL[:, :, :-1], sr[:, :, :-1], rhoL[:, :, 1:], sr[:, :, 1:], f, dy * dz, dx)
+        de = _face_value(eL[:, :, :-1], se[:, :, :-1], eL[:, :, 1:], se[:, :, 1:], f, dy * dz, dx)
+    else:
+        dr = np.where(f > 0, rhoL[:, :, :-1], rhoL[:, :, 1:])
+        de = np.where(f > 0, eL[:, :, :-1], eL[:, :, 1:])
     mux[:, :, 1:nx] = dr * f
     exf[:, :, 1:nx] = dr * f * de
     muy = np.zeros_like(dvy)
     eyf = np.zeros_like(dvy)
     f = dvy[:, 1:ny, :]
-    dr = np.where(f > 0, rhoL[:, :-1, :], rhoL[:, 1:, :])
-    de = np.where(f > 0, eL[:, :-1, :], eL[:, 1:, :])
+    if o2:
+        sr, se = _limited_slopes(rhoL, 1, dy), _limited_slopes(eL, 1, dy)
+        dr = _face_value(rhoL[:, :-1, :], sr[:, :-1, :], rhoL[:, 1:, :], sr[:, 1:, :], f, dz * dx, dy)
+        de = _face_value(eL[:, :-1, :], se[:, :-1, :], eL[:, 1:, :], se[:, 1:, :], f, dz * dx, dy)
+    else:
+        dr = np.where(f > 0, rhoL[:, :-1, :], rhoL[:, 1:, :])
+        de = np.where(f > 0, eL[:, :-1, :], eL[:, 1:, :])
     muy[:, 1:ny, :] = dr * f
     eyf[:, 1:ny, :] = dr * f * de
     muz = np.zeros_like(dvz)
     ezf = np.zeros_like(dvz)
     f = dvz[1:nz]
-    dr = np.where(f > 0, rhoL[:-1], rhoL[1:])
-    de = np.where(f > 0, eL[:-1], eL[1:])
+    if o2:
+        sr, se = _limited_slopes(rhoL, 0, dz), _limited_slopes(eL, 0, dz)
+        dr = _face_value(rhoL[:-1], sr[:-1], rhoL[1:], sr[1:], f, dx * dy, dz)
+        de = _face_value(eL[:-1], se[:-1], eL[1:], se[1:], f, dx * dy, dz)
+    else:
+        dr = np.where(f > 0, rhoL[:-1], rhoL[1:])
+        de = np.where(f > 0, eL[:-1], eL[1:])
     muz[1:nz] = dr * f
     ezf[1:nz] = dr * f * de
     netm = (mux[:, :, 1:] - mux[:, :, :-1]) + (muy[:, 1:, :] - muy[:, :-1, :]) + (muz[1:] - muz[:-1])
@@ -165,16 +213,31 @@ def step(grid, rho, e, u, v, w, t):
     phy = 0.125 * (syc[:-1, :, :-1] + syc[:-1, :, 1:] + syc[1:, :, :-1] + syc[1:, :, 1:])  # (nz+1, ny, nx+1)
     szc = np.pad(muz[:-1] + muz[1:], ((0, 0), (1, 1), (1, 1)))
     phz = 0.125 * (szc[:, :-1, :-1] + szc[:, :-1, 1:] + szc[:, 1:, :-1] + szc[:, 1:, 1:])  # (nz, ny+1, nx+1)
+    # dual swept volumes on node edges, averaged like the dual mass fluxes
+    sxv = np.pad(dvx[:, :, :-1] + dvx[:, :, 1:], ((1, 1), (1, 1), (0, 0)))
+    dvpx = 0.125 * (sxv[:-1, :-1] + sxv[:-1, 1:] + sxv[1:, :-1] + sxv[1:, 1:])
+    syv = np.pad(dvy[:, :-1, :] + dvy[:, 1:, :], ((1, 1), (0, 0), (1, 1)))
+    dvpy = 0.125 * (syv[:-1, :, :-1] + syv[:-1, :, 1:] + syv[1:, :, :-1] + syv[1:, :, 1:])
+    szv = np.pad(dvz[:-1] + dvz[1:], ((0, 0), (1, 1), (1, 1)))
+    dvpz = 0.125 * (szv[:, :-1, :-1] + szv[:, :-1, 1:] + szv[:, 1:, :-1] + szv[:, 1:, 1:])
     vel = np.stack([u1, v1, w1], axis=-1)
     Pm = mp[..., None] * vel
     K = 0.5 * mp * (u1 * u1 + v1 * v1 + w1 * w1)
-    for axis, ph in ((2, phx), (1, phy), (0, phz)):
+    for axis, ph, dvp, hh, area in ((2, phx, dvpx, dx, dy * dz), (1, phy, dvpy, dy, dz * dx),
+                                    (0, phz, dvpz, dz, dx * dy)):
         lo = [slice(None)] * 3
         hi = [slice(None)] * 3
         lo[axis] = slice(0, -1)
         hi[axis] = slice(1, None)
         lo, hi = tuple(lo), tuple(hi)
-        ud = np.where((ph > 0)[..., None], vel[lo], vel[hi])
+        if o2:
+            # the donor's swept slab lies on the flux's side: sign from phi
+            sdv = np.where(ph > 0, np.abs(dvp), -np.abs(dvp))
+            ud = np.stack([_face_value(vel[..., m][lo], _limited_slopes(vel[..., m], axis, hh)[lo],
+                                       vel[..., m][hi], _limited_slopes(vel[..., m], axis, hh)[hi],
+                                       sdv, area, hh) for m in range(3)], axis=-1)
+        else:
+            ud = np.where((ph > 0)[..., None], vel[lo], vel[hi])
         Pi = ph[..., None] * ud
         ka = ph * 0.5 * np.sum(ud * ud, axis=-1)
         Pm[lo] -= Pi

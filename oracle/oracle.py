@@ -26,7 +26,7 @@ class _Config(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
                 ("lo", C.c_double * 3), ("hi", C.c_double * 3),
                 ("gamma", C.c_double), ("cfl", C.c_double), ("cq", C.c_double),
-                ("cl", C.c_double), ("t_end", C.c_double)]
+                ("cl", C.c_double), ("t_end", C.c_double), ("order", C.c_int32)]
 
 
 def lib():
@@ -61,6 +61,10 @@ def lib():
         L.orc_derived.argtypes = [cfg, C.c_void_p, P, P, P, P, P, P, P]
         L.orc_face_swept_volume.restype = C.c_double
         L.orc_face_swept_volume.argtypes = [P, C.c_double, C.c_double]
+        L.orc_vanleer.restype = C.c_double
+        L.orc_vanleer.argtypes = [C.c_double, C.c_double]
+        L.orc_donor_value.restype = C.c_double
+        L.orc_donor_value.argtypes = [C.c_double] * 4
         _lib = L
     return _lib
 
@@ -73,7 +77,7 @@ def _ptr(a):
 @dataclass
 class Grid:
     """Mesh and scheme constants of one run (defaults: gamma 1.4, CFL 0.5,
-    quadratic / linear viscosity coefficients 1.0 / 0.5)."""
+    quadratic / linear viscosity coefficients 1.0 / 0.5, first-order remap)."""
     nx: int
     ny: int
     nz: int
@@ -84,11 +88,12 @@ class Grid:
     cq: float = 1.0
     cl: float = 0.5
     t_end: float = 1.0
+    order: int = 1
 
     def c(self):
         return _Config(self.nx, self.ny, self.nz, (C.c_double * 3)(*self.lo),
                        (C.c_double * 3)(*self.hi), self.gamma, self.cfl, self.cq, self.cl,
-                       self.t_end)
+                       self.t_end, self.order)
 
     @property
     def cell_shape(self):
@@ -236,3 +241,14 @@ def face_swept_volume(d, h1, h2):
     corners (s,t) = (0,0), (1,0), (0,1), (1,1) and components (normal, t1, t2)."""
     d = np.ascontiguousarray(d, dtype=np.float64).reshape(4, 3)
     return lib().orc_face_swept_volume(_ptr(d), h1, h2)
+
+
+def vanleer(a_minus, a_plus):
+    """The oracle's slope limiter (second-order remap)."""
+    return lib().orc_vanleer(a_minus, a_plus)
+
+
+def donor_value(q, slope, h, dvA):
+    """The oracle's donor value at a swept volume's centroid (second-order
+    remap): dvA is the swept volume over the face area, signed."""
+    return lib().orc_donor_value(q, slope, h, dvA)

@@ -51,6 +51,7 @@ typedef struct {
   double lo[3], hi[3];
   double gamma, cfl, cq, cl;
   double t_end;
+  int32_t order; /* remap order: 1 (donor cell) or 2 (limited linear) */
 } orc_config;
 
 /* Scratch arrays of one step. Face arrays: x faces (nx+1)*ny*nz,
@@ -66,6 +67,7 @@ typedef struct {
   double *M, *E, *epre, *rn;                /* cells; rn = new density */
   double *P1, *P2, *P3, *K, *mn, *dK;       /* nodes */
   double *un, *vn, *wn;                     /* nodes: new velocity */
+  double *sr[3], *se[3];                    /* cells: limited slopes of rho^L, e^L */
 } orc_ws;
 
 /* ------------------------------------------------------------------ */
@@ -147,8 +149,9 @@ orc_ws *orc_ws_create(const orc_config *g) {
   size_t nn = (size_t)(NX + 1) * (NY + 1) * (NZ + 1);
   size_t nfx = (size_t)(NX + 1) * NY * NZ, nfy = (size_t)NX * (NY + 1) * NZ,
          nfz = (size_t)NX * NY * (NZ + 1);
-  double **cells[] = {&w->p, &w->c, &w->q, &w->D, &w->ps, &w->mc, &w->eL, &w->VL,
-                      &w->rhoL, &w->M, &w->E, &w->epre, &w->rn};
+  double **cells[] = {&w->p,  &w->c,  &w->q,     &w->D,     &w->ps,    &w->mc,    &w->eL,
+                      &w->VL, &w->rhoL, &w->M, &w->E,  &w->epre,  &w->rn,    &w->sr[0],
+                      &w->sr[1], &w->sr[2], &w->se[0], &w->se[1], &w->se[2]};
   double **nodes[] = {&w->mp, &w->u1, &w->v1, &w->w1, &w->ub, &w->vb, &w->wb, &w->P1,
                       &w->P2, &w->P3, &w->K, &w->mn, &w->dK, &w->un, &w->vn, &w->wn};
   int ok = 1;
@@ -174,7 +177,8 @@ void orc_ws_destroy(orc_ws *w) {
   double *all[] = {w->p, w->c, w->q, w->D, w->ps, w->mc, w->mp, w->u1, w->v1, w->w1,
                    w->ub, w->vb, w->wb, w->eL, w->VL, w->rhoL, w->dvx, w->dvy, w->dvz,
                    w->mux, w->muy, w->muz, w->ex, w->ey, w->ez, w->M, w->E, w->epre, w->rn,
-                   w->P1, w->P2, w->P3, w->K, w->mn, w->dK, w->un, w->vn, w->wn};
+                   w->P1, w->P2, w->P3, w->K, w->mn, w->dK, w->un, w->vn, w->wn,
+                   w->sr[0], w->sr[1], w->sr[2], w->se[0], w->se[1], w->se[2]};
   for (size_t a = 0; a < sizeof(all) / sizeof(all[0]); a++) free(all[a]);
   free(w);
 }
@@ -185,6 +189,7 @@ static int config_valid(const orc_config *g) {
     if (!(g->hi[a] > g->lo[a])) return 0;
   if (!(g->gamma > 1.0) || !(g->cfl > 0.0) || !(g->cfl < 1.0)) return 0;
   if (!(g->cq >= 0.0) || !(g->cl >= 0.0) || !(g->t_end >= 0.0)) return 0;
+  if (g->order != 1 && g->order != 2) return 0;
   return 1;
 }
 
@@ -480,17 +485,78 @@ static void donor_flux(const orc_ws *W, double dv, size_t L, size_t R, double *m
   *eps = *mu * W->eL[dn];
 }
 
+/* Second-order remap (order 2): the donor's value is taken from a limited
+ * linear reconstruction along the face normal, at the centroid of the swept
+ * volume. The harmonic (van Leer) limiter of the one-sided differences
+ * a_minus, a_plus (per unit length): zero unless they share a sign. */
+double orc_vanleer(double a_minus, double a_plus) {
+  return (a_minus * a_plus > 0.0) ? 2.0 * a_minus * a_plus / (a_minus + a_plus) : 0.0;
+}
+
+/* Donor value at the swept volume's centroid: the donor's value q plus its
+ * slope times the signed distance from its centre. The swept slab of
+ * thickness |dvA| (= |swept volume| / face area) lies at the donor's end
+ * next to the face, so its centroid is (h - |dvA|) / 2 from the donor's
+ * centre: toward +axis when the donor is the lower cell (dvA > 0), toward
+ * -axis when it is the upper one. */
+double orc_donor_value(double q, double slope, double h, double dvA) {
+  const double off = 0.5 * (h - fabs(dvA));
+  return (dvA > 0.0) ? q + slope * off : q - slope * off;
+}
+
+/* limited slopes of rho^L and e^L in every cell along each axis (zero in a
+ * cell whose neighbour along that axis is a wall) */
+static void stage_cell_slopes(const orc_config *g, orc_ws *W) {
+  double hs[3];
+  spacing(g, &hs[0], &hs[1], &hs[2]);
+#pragma omp parallel for schedule(static)
+  for (int k = 0; k < NZ; k++)
+    for (int j = 0; j < NY; j++)
+      for (int i = 0; i < NX; i++) {
+        const size_t c = CI(g, i, j, k);
+        for (int a = 0; a < 3; a++) {
+          const int di = a == 0, dj = a == 1, dk = a == 2;
+          double sr = 0.0, se = 0.0;
+          if (cell_exists(g, i - di, j - dj, k - dk) && cell_exists(g, i + di, j + dj, k + dk)) {
+            const size_t cm = CI(g, i - di, j - dj, k - dk), cp = CI(g, i + di, j + dj, k + dk);
+            sr = orc_vanleer((W->rhoL[c] - W->rhoL[cm]) / hs[a], (W->rhoL[cp] - W->rhoL[c]) / hs[a]);
+            se = orc_vanleer((W->eL[c] - W->eL[cm]) / hs[a], (W->eL[cp] - W->eL[c]) / hs[a]);
+          }
+          W->sr[a][c] = sr;
+          W->se[a][c] = se;
+        }
+      }
+}
+
+/* second-order flux through an interior face normal to `axis` */
+static void donor_flux2(const orc_ws *W, int axis, double h, double area, double dv, size_t L, size_t R,
+                        double *mu, double *eps) {
+  const size_t dn = (dv > 0.0) ? L : R;
+  const double dvA = dv / area;
+  const double rf = orc_donor_value(W->rhoL[dn], W->sr[axis][dn], h, dvA);
+  const double ef = orc_donor_value(W->eL[dn], W->se[axis][dn], h, dvA);
+  *mu = rf * dv;
+  *eps = *mu * ef;
+}
+
 static int stage_cell_remap(const orc_config *g, const double *rho, orc_ws *W) {
   double dx, dy, dz;
   spacing(g, &dx, &dy, &dz);
   const double V0 = dx * dy * dz;
+  const int o2 = g->order == 2;
+  if (o2) stage_cell_slopes(g, W);
 #pragma omp parallel for schedule(static)
   for (int k = 0; k < NZ; k++)
     for (int j = 0; j < NY; j++)
       for (int i = 0; i <= NX; i++) {
         size_t f = FXI(g, i, j, k);
         double mu = 0.0, eps = 0.0;
-        if (i > 0 && i < NX) donor_flux(W, W->dvx[f], CI(g, i - 1, j, k), CI(g, i, j, k), &mu, &eps);
+        if (i > 0 && i < NX) {
+          if (o2)
+            donor_flux2(W, 0, dx, dy * dz, W->dvx[f], CI(g, i - 1, j, k), CI(g, i, j, k), &mu, &eps);
+          else
+            donor_flux(W, W->dvx[f], CI(g, i - 1, j, k), CI(g, i, j, k), &mu, &eps);
+        }
         W->mux[f] = mu; W->ex[f] = eps;
       }
 #pragma omp parallel for schedule(static)
@@ -499,7 +565,12 @@ static int stage_cell_remap(const orc_config *g, const double *rho, orc_ws *W) {
       for (int i = 0; i < NX; i++) {
         size_t f = FYI(g, i, j, k);
         double mu = 0.0, eps = 0.0;
-        if (j > 0 && j < NY) donor_flux(W, W->dvy[f], CI(g, i, j - 1, k), CI(g, i, j, k), &mu, &eps);
+        if (j > 0 && j < NY) {
+          if (o2)
+            donor_flux2(W, 1, dy, dz * dx, W->dvy[f], CI(g, i, j - 1, k), CI(g, i, j, k), &mu, &eps);
+          else
+            donor_flux(W, W->dvy[f], CI(g, i, j - 1, k), CI(g, i, j, k), &mu, &eps);
+        }
         W->muy[f] = mu; W->ey[f] = eps;
       }
 #pragma omp parallel for schedule(static)
@@ -508,7 +579,12 @@ static int stage_cell_remap(const orc_config *g, const double *rho, orc_ws *W) {
       for (int i = 0; i < NX; i++) {
         size_t f = FZI(g, i, j, k);
         double mu = 0.0, eps = 0.0;
-        if (k > 0 && k < NZ) donor_flux(W, W->dvz[f], CI(g, i, j, k - 1), CI(g, i, j, k), &mu, &eps);
+        if (k > 0 && k < NZ) {
+          if (o2)
+            donor_flux2(W, 2, dz, dx * dy, W->dvz[f], CI(g, i, j, k - 1), CI(g, i, j, k), &mu, &eps);
+          else
+            donor_flux(W, W->dvz[f], CI(g, i, j, k - 1), CI(g, i, j, k), &mu, &eps);
+        }
         W->muz[f] = mu; W->ez[f] = eps;
       }
   int bad = 0;
@@ -557,6 +633,51 @@ static double dual_flux(const orc_config *g, const orc_ws *W, int axis, int i, i
   return 0.125 * s;
 }
 
+/* swept volume of the dual face between node (i,j,k) and its +axis
+ * neighbour (order 2): one eighth of the sum of the lower plus upper face
+ * swept volumes of the same cells as in dual_flux */
+static double dual_swept(const orc_config *g, const orc_ws *W, int axis, int i, int j, int k) {
+  double s = 0.0;
+  for (int o2 = -1; o2 <= 0; o2++)
+    for (int o1 = -1; o1 <= 0; o1++) {
+      int ci = i, cj = j, ck = k;
+      if (axis == 0) { cj += o1; ck += o2; }
+      if (axis == 1) { ci += o1; ck += o2; }
+      if (axis == 2) { ci += o1; cj += o2; }
+      if (!cell_exists(g, ci, cj, ck)) continue;
+      if (axis == 0) s += W->dvx[FXI(g, ci, cj, ck)] + W->dvx[FXI(g, ci + 1, cj, ck)];
+      if (axis == 1) s += W->dvy[FYI(g, ci, cj, ck)] + W->dvy[FYI(g, ci, cj + 1, ck)];
+      if (axis == 2) s += W->dvz[FZI(g, ci, cj, ck)] + W->dvz[FZI(g, ci, cj, ck + 1)];
+    }
+  return 0.125 * s;
+}
+
+/* donor velocity of the edge from node (i,j,k) to its +axis neighbour with
+ * mass flux phi: node u' (order 1), or its limited linear reconstruction
+ * along the edge at the dual swept volume's centroid (order 2; slopes zero
+ * at a node whose neighbour along the axis is outside the mesh) */
+static void donor_velocity(const orc_config *g, const orc_ws *W, int axis, int i, int j, int k, double phi,
+                           double out[3]) {
+  const int di = axis == 0, dj = axis == 1, dk = axis == 2;
+  const int ni = (phi > 0.0) ? i : i + di, nj = (phi > 0.0) ? j : j + dj, nk = (phi > 0.0) ? k : k + dk;
+  const size_t dn = NI(g, ni, nj, nk);
+  const double *u[3] = {W->u1, W->v1, W->w1};
+  for (int m = 0; m < 3; m++) out[m] = u[m][dn];
+  if (g->order != 2) return;
+  double hs[3];
+  spacing(g, &hs[0], &hs[1], &hs[2]);
+  const double area = hs[(axis + 1) % 3] * hs[(axis + 2) % 3];
+  /* the dual swept volume and the flux take the same sign convention */
+  const double dvA = dual_swept(g, W, axis, i, j, k) / area;
+  const double sgn_dvA = (phi > 0.0) ? fabs(dvA) : -fabs(dvA);
+  if (!node_exists(g, ni - di, nj - dj, nk - dk) || !node_exists(g, ni + di, nj + dj, nk + dk)) return;
+  const size_t nm = NI(g, ni - di, nj - dj, nk - dk), np = NI(g, ni + di, nj + dj, nk + dk);
+  for (int m = 0; m < 3; m++) {
+    const double sl = orc_vanleer((u[m][dn] - u[m][nm]) / hs[axis], (u[m][np] - u[m][dn]) / hs[axis]);
+    out[m] = orc_donor_value(u[m][dn], sl, hs[axis], sgn_dvA);
+  }
+}
+
 static int stage_node_remap(const orc_config *g, orc_ws *W) {
   int bad = 0;
 #pragma omp parallel for schedule(static) reduction(| : bad)
@@ -573,16 +694,18 @@ static int stage_node_remap(const orc_config *g, orc_ws *W) {
           /* edge to the +axis neighbour: outflow from this node */
           if (node_exists(g, i + di, j + dj, k + dk)) {
             double phi = dual_flux(g, W, axis, i, j, k);
-            size_t dn = (phi > 0.0) ? n : NI(g, i + di, j + dj, k + dk);
-            double ud = W->u1[dn], vd = W->v1[dn], wd = W->w1[dn];
+            double dv[3];
+            donor_velocity(g, W, axis, i, j, k, phi, dv);
+            double ud = dv[0], vd = dv[1], wd = dv[2];
             P[0] -= phi * ud; P[1] -= phi * vd; P[2] -= phi * wd;
             K -= phi * 0.5 * (ud * ud + vd * vd + wd * wd);
           }
           /* edge from the -axis neighbour: inflow to this node */
           if (node_exists(g, i - di, j - dj, k - dk)) {
             double phi = dual_flux(g, W, axis, i - di, j - dj, k - dk);
-            size_t dn = (phi > 0.0) ? NI(g, i - di, j - dj, k - dk) : n;
-            double ud = W->u1[dn], vd = W->v1[dn], wd = W->w1[dn];
+            double dv[3];
+            donor_velocity(g, W, axis, i - di, j - dj, k - dk, phi, dv);
+            double ud = dv[0], vd = dv[1], wd = dv[2];
             P[0] += phi * ud; P[1] += phi * vd; P[2] += phi * wd;
             K += phi * 0.5 * (ud * ud + vd * vd + wd * wd);
           }
