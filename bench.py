@@ -128,14 +128,14 @@ def measured_traffic(n, shape):
 
 
 # ---- workloads -----------------------------------------------------------------
-def headline(n, steps, warmup, precision, tuned=True, fixed=None):
+def headline(n, steps, warmup, precision, tuned=True, fixed=None, order=1):
     """(ms per step from HIP events around `steps` async steps, final t,
     per-kernel ms, launch shape). With `tuned`, the autotuner first picks the
     launch shape of the step kernels for this mesh and precision."""
     import torch
     from paper_2209_01983_amd import sale, tune
 
-    cfg = sale.make_config(n, n, n, hi=(1.2, 1.2, 1.2), t_end=1.0, precision=precision)
+    cfg = sale.make_config(n, n, n, hi=(1.2, 1.2, 1.2), t_end=1.0, precision=precision, remap_order=order)
     shape = {"rows_a": 16, "rows_b": 16, "target": 0}
     if fixed:
         shape = dict(zip(("rows_a", "rows_b", "target"), fixed))
@@ -381,6 +381,12 @@ def main():
                      "step_kernel_ms": step_kernel_ms, "dominant_kernel": dominant["name"],
                      "kernels": kernels},
     }
+    say("headline fp64, second-order remap", n)
+    ms2, _, k2, _ = headline(n, a.steps, a.warmup, sale.SALE_FP64, tuned=False,
+                             fixed=(shape64["rows_a"], shape64["rows_b"], shape64["target"]), order=2)
+    out["remap_order2"] = {"value": cells * 1e3 / ms2, "unit": "cell-updates/s", "ms_per_step": ms2,
+                           "kernel_ms": {"k_begin": k2[0], "k_lagrange": k2[1], "remap (4 passes)": k2[2]},
+                           "precision": "fp64", "note": "limited linear donor values; direct multi-pass remap"}
     if not a.quick:
         say("sod latency")
         out["latency"] = sod_latency(50)

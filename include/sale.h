@@ -101,6 +101,11 @@ typedef struct {
   double t_end;             /* end time >= 0                                */
   int32_t precision;        /* SALE_FP64 | SALE_MIXED32                     */
   int32_t bc[6];            /* per face (-x,+x,-y,+y,-z,+z): SALE_BC_REFLECT */
+  int32_t remap_order;      /* 1 (or 0): first-order donor cell; 2: donor
+                               values from limited linear profiles at the
+                               swept volume's centroid (van Leer slopes),
+                               cells and dual mesh; single runs only (a
+                               pool admits order 1)                         */
 } sale_config;
 
 typedef struct {

@@ -73,6 +73,7 @@ int validate_config(const sale_config *c) {
   if (c->precision != SALE_FP64 && c->precision != SALE_MIXED32) return SALE_EINVAL;
   for (int a = 0; a < 6; a++)
     if (c->bc[a] != SALE_BC_REFLECT) return SALE_EINVAL;
+  if (c->remap_order < 0 || c->remap_order > 2) return SALE_EINVAL;
   // the step kernels address each field array with 32-bit byte offsets
   const int64_t nnode = (int64_t)(c->nx + 1) * (c->ny + 1) * (c->nz + 1);
   if (nnode * (int64_t)sizeof(double) >= ((int64_t)1 << 32)) return SALE_EINVAL;
@@ -108,6 +109,7 @@ Mesh make_mesh(const sale_config *c) {
   m.hdy = 0.5 * m.dy;
   m.hdz = 0.5 * m.dz;
   m.ncell = (int64_t)c->nx * c->ny * c->nz;
+  m.order = c->remap_order == 2 ? 2 : 1;
   m.nnode = (int64_t)(c->nx + 1) * (c->ny + 1) * (c->nz + 1);
   return m;
 }
@@ -603,6 +605,7 @@ int sale_pool_admit(sale_pool *p, const sale_config *cfg, const sale_problem *pr
   if (rc != SALE_OK) return rc;
   if (cfg->precision != p->precision) return SALE_EINVAL;
   const Mesh m = make_mesh(cfg);
+  if (m.order != 1) return SALE_EINVAL;  // the persistent kernel remaps to first order
   if ((rc = validate_problem(prob, m)) != SALE_OK) return rc;
   int s = -1;
   for (int k = 0; k < p->max_runs; k++)

@@ -66,6 +66,20 @@ __device__ __forceinline__ R divergence(const Mesh &m, R xa, R xb, R ya, R yb, R
   return fma(R(m.az), zb - za, fma(R(m.ay), ya + yb, R(m.ax) * (xa + xb))) * R(m.iV0);
 }
 
+// divergence D of cell (i,j,k) of state s, formed as in the step kernels
+template <typename R>
+__device__ __forceinline__ R state_divergence(const Mesh &m, const State<R> &s, int i, int j, int k) {
+  R x[2], y[2], z[2];
+#pragma unroll
+  for (int c = 0; c < 2; c++) {
+    auto at = [&](const R *f, int a, int b) { return f[nidx(m, i + a, j + b, k + c)]; };
+    x[c] = (at(s.u, 1, 0) - at(s.u, 0, 0)) + (at(s.u, 1, 1) - at(s.u, 0, 1));
+    y[c] = (at(s.v, 0, 1) - at(s.v, 0, 0)) + (at(s.v, 1, 1) - at(s.v, 1, 0));
+    z[c] = ((at(s.w, 0, 0) + at(s.w, 1, 0)) + at(s.w, 0, 1)) + at(s.w, 1, 1);
+  }
+  return divergence(m, x[0], x[1], y[0], y[1], z[0], z[1]);
+}
+
 // node speed |u|, same bits in every kernel
 template <typename R>
 __device__ __forceinline__ R speed(R u, R v, R w) {

@@ -25,6 +25,7 @@ struct Mesh {
   double hyz, hzx, hxy;      // face areas dy dz, dz dx, dx dy
   double hdx, hdy, hdz;      // half spacings dx/2, dy/2, dz/2
   int64_t ncell, nnode;
+  int order;                 // remap order: 1 donor cell, 2 limited linear
 };
 
 // Device control block (one per run). `done` is decided once per step by the
@@ -73,6 +74,17 @@ struct Geo {
 // Workspace of one run: two states (ping-pong), the Lagrangian end velocity
 // u' and the Lagrangian cell results, reduction partials, and one scratch
 // array of max(cells, nodes) doubles (conversions, derived fields).
+// Intermediates of the second-order remap (null for order 1): face mass and
+// internal-energy fluxes through each cell's three lower faces, the cells' new
+// masses and pre-fix energies, and the nodes' kinetic-energy defects per unit
+// new mass.
+template <typename R>
+struct Rem2 {
+  R *mu[3], *eps[3];
+  R *M, *epre;
+  R *dk;
+};
+
 template <typename R>
 struct Work {
   State<R> s[2];
@@ -80,7 +92,14 @@ struct Work {
   Geo<R> geo;
   double *partial;
   double *scratch;
+  Rem2<R> r2;
 };
+
+// The second-order remap (multi-pass kernels in sale_remap2.hip): from the
+// Lagrangian results in w.geo / u' into w.s[1 - cur], then the next signal
+// speed into ctl.
+template <typename R>
+hipError_t launch_remap2(const Mesh &m, Ctl *ctl, const Work<R> &w, int cur, hipStream_t s);
 
 // Launch decomposition of a z-marching step kernel: tiles of 32 x CH columns,
 // the z extent split into segments so that the grid fills the chip.

@@ -67,20 +67,6 @@ __device__ __forceinline__ void node_ijk(const Mesh &m, int64_t n, int &i, int &
   k = (int)(r / (m.ny + 1));
 }
 
-// divergence D of cell (i,j,k) of state s, formed as in the step kernels
-template <typename R>
-__device__ __forceinline__ R state_divergence(const Mesh &m, const State<R> &s, int i, int j, int k) {
-  R x[2], y[2], z[2];
-#pragma unroll
-  for (int c = 0; c < 2; c++) {
-    auto at = [&](const R *f, int a, int b) { return f[nidx(m, i + a, j + b, k + c)]; };
-    x[c] = (at(s.u, 1, 0) - at(s.u, 0, 0)) + (at(s.u, 1, 1) - at(s.u, 0, 1));
-    y[c] = (at(s.v, 0, 1) - at(s.v, 0, 0)) + (at(s.v, 1, 1) - at(s.v, 1, 0));
-    z[c] = ((at(s.w, 0, 0) + at(s.w, 1, 0)) + at(s.w, 0, 1)) + at(s.w, 1, 1);
-  }
-  return divergence(m, x[0], x[1], y[0], y[1], z[0], z[1]);
-}
-
 template <typename R>
 __global__ __launch_bounds__(TPB) void k_signal(Mesh m, Ctl *ctl, State<R> s) {
   const int64_t c = blockIdx.x * (int64_t)TPB + threadIdx.x;
@@ -337,8 +323,9 @@ size_t workspace_bytes(const Mesh &m) {
   const size_t cR = align256((size_t)m.ncell * sizeof(R)), nR = align256((size_t)m.nnode * sizeof(R));
   const size_t sD = align256((size_t)(m.ncell > m.nnode ? m.ncell : m.nnode) * sizeof(double));
   // ctl | 2 states | u' | rho^L, e^L | 3 swept volumes | partials | scratch
+  const size_t r2 = m.order == 2 ? 8 * cR + nR : 0;  // second-order remap intermediates
   return align256(sizeof(Ctl)) + 2 * (2 * cR + 3 * nR) + 3 * nR + 2 * cR + 3 * cR +
-         align256(3 * TOT_BLOCKS * sizeof(double)) + sD;
+         align256(3 * TOT_BLOCKS * sizeof(double)) + sD + r2;
 }
 
 template <typename R>
@@ -375,6 +362,14 @@ void layout(const Mesh &m, void *ws, Ctl **ctl, Work<R> *w) {
   w->geo.dvz = takeR(cR);
   w->partial = takeD(align256(3 * TOT_BLOCKS * sizeof(double)));
   w->scratch = takeD(sD);
+  w->r2 = Rem2<R>{};
+  if (m.order == 2) {
+    for (int a = 0; a < 3; a++) w->r2.mu[a] = takeR(cR);
+    for (int a = 0; a < 3; a++) w->r2.eps[a] = takeR(cR);
+    w->r2.M = takeR(cR);
+    w->r2.epre = takeR(cR);
+    w->r2.dk = takeR(nR);
+  }
 }
 
 // ---- launchers ----------------------------------------------------------------------------
@@ -469,12 +464,17 @@ hipError_t launch_step(const Mesh &m, Ctl *ctl, const Work<R> &w, int cur, const
     default: launch_lagrange<R, 16>(a, s); break;
   }
   if (ev && e == hipSuccess) e = hipEventRecord(ev[2], s);
-  switch (L.rows_b) {
-    case 8: launch_remap<R, 8>(a, s); break;
-    case 12: launch_remap<R, 12>(a, s); break;
-    case 24: launch_remap<R, 24>(a, s); break;
-    case 32: launch_remap<R, 32>(a, s); break;
-    default: launch_remap<R, 16>(a, s); break;
+  if (m.order == 2) {
+    const hipError_t r = launch_remap2<R>(m, ctl, w, cur, s);
+    if (r != hipSuccess) return r;
+  } else {
+    switch (L.rows_b) {
+      case 8: launch_remap<R, 8>(a, s); break;
+      case 12: launch_remap<R, 12>(a, s); break;
+      case 24: launch_remap<R, 24>(a, s); break;
+      case 32: launch_remap<R, 32>(a, s); break;
+      default: launch_remap<R, 16>(a, s); break;
+    }
   }
   if (ev && e == hipSuccess) e = hipEventRecord(ev[3], s);
   const hipError_t l = hipGetLastError();

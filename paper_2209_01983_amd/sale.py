@@ -47,7 +47,8 @@ class sale_config(C.Structure):
                 ("lo", C.c_double * 3), ("hi", C.c_double * 3),
                 ("gamma", C.c_double), ("cfl", C.c_double),
                 ("c_quad", C.c_double), ("c_lin", C.c_double),
-                ("t_end", C.c_double), ("precision", C.c_int32), ("bc", C.c_int32 * 6)]
+                ("t_end", C.c_double), ("precision", C.c_int32), ("bc", C.c_int32 * 6),
+                ("remap_order", C.c_int32)]
 
 
 class sale_problem(C.Structure):
@@ -214,9 +215,9 @@ def sale_pool_destroy(pool) -> None:
 
 # ---- helpers ------------------------------------------------------------------------
 def make_config(nx, ny, nz, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), gamma=1.4, cfl=0.5,
-                c_quad=1.0, c_lin=0.5, t_end=1.0, precision=SALE_FP64) -> sale_config:
+                c_quad=1.0, c_lin=0.5, t_end=1.0, precision=SALE_FP64, remap_order=1) -> sale_config:
     return sale_config(nx, ny, nz, (C.c_double * 3)(*lo), (C.c_double * 3)(*hi), gamma, cfl, c_quad,
-                       c_lin, t_end, precision, (C.c_int32 * 6)(*([SALE_BC_REFLECT] * 6)))
+                       c_lin, t_end, precision, (C.c_int32 * 6)(*([SALE_BC_REFLECT] * 6)), remap_order)
 
 
 def sod_problem(x_split=0.5, rhoL=1.0, pL=1.0, rhoR=0.125, pR=0.1, t0=0.0, step0=0) -> sale_problem:

@@ -53,7 +53,8 @@ def assert_parity(gpu, ora, tol=TOL64, what=""):
 
 def grid_of(cfg) -> "orc.Grid":
     return orc.Grid(cfg.nx, cfg.ny, cfg.nz, lo=tuple(cfg.lo), hi=tuple(cfg.hi), gamma=cfg.gamma,
-                    cfl=cfg.cfl, cq=cfg.c_quad, cl=cfg.c_lin, t_end=cfg.t_end)
+                    cfl=cfg.cfl, cq=cfg.c_quad, cl=cfg.c_lin, t_end=cfg.t_end,
+                    order=2 if cfg.remap_order == 2 else 1)
 
 
 def oracle_state(fields: dict, t=0.0, step=0) -> "orc.State":

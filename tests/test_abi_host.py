@@ -30,14 +30,15 @@ def test_library_exports_every_declared_function():
 
 
 def test_struct_layout_matches_header_sizes():
-    # int32 x3, pad, 6 doubles, 5 doubles, int32, int32[6], tail pad
+    # int32 x3, pad, 6 doubles, 5 doubles, int32, int32[6], int32 remap order
     assert C.sizeof(sale.sale_config) == 12 + 4 + 48 + 40 + 4 + 24 + 4
     assert C.sizeof(sale.sale_problem) == 8 + 40 + 24 + 40 + 8 + 8 + 8
 
 
 @pytest.mark.parametrize("bad", [
     dict(nx=0), dict(ny=-1), dict(nx=812, ny=812, nz=812), dict(gamma=1.0), dict(cfl=0.0), dict(cfl=1.0), dict(c_quad=-1.0),
-    dict(t_end=-1.0), dict(precision=7), dict(hi=(0.0, 1.0, 1.0)),
+    dict(t_end=-1.0), dict(precision=7), dict(hi=(0.0, 1.0, 1.0)), dict(remap_order=3),
+    dict(remap_order=-1),
 ])
 def test_invalid_config_rejected(bad):
     kw = dict(nx=4, ny=4, nz=4)
