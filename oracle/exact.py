@@ -10,6 +10,9 @@
   the self-similar point blast, R(t) = (E t^2 / (alpha rho0))^(1/5), obtained
   by integrating the similarity ODEs inward from the strong-shock
   Rankine-Hugoniot state and evaluating the energy integral.
+* Noh implosion (Sec. I-D lists it among ScalSALE's problems; Noh, J. Comput.
+  Phys. 72, 1987): cold gas streaming at speed u0 toward the origin in
+  1, 2 or 3 dimensions, closed form.
 
 Neither part depends on the oracle or on the HIP path.
 """
@@ -190,3 +193,41 @@ def sedov_alpha(gamma=1.4, eta_min=1e-6):
 def sedov_radius(t, E=1.0, rho0=1.0, gamma=1.4):
     """Shock radius of the full-space point blast of energy E at time t."""
     return (E * t * t / (sedov_alpha(gamma) * rho0)) ** 0.2
+
+
+# --------------------------------------------------------------------------
+# Noh: closed-form implosion
+# --------------------------------------------------------------------------
+class NohExact:
+    """Cold ideal gas (p = 0) of density rho0 moving at speed u0 toward the
+    origin in `dims` dimensions (1 planar, 2 cylindrical, 3 spherical).
+
+    Ahead of the shock the gas keeps its velocity -u0, so continuity with a
+    converging cross-section r^(dims-1) gives rho = rho0 (1 + u0 t / r)^(dims-1)
+    there. Behind it the gas is at rest. A strong shock in a cold gas
+    compresses by (gamma+1)/(gamma-1); mass conservation in the shock frame
+    (preshock speed u0 + D, postshock speed D) fixes the shock speed
+    D = u0 (gamma-1)/2 and the postshock density
+    rho0 ((gamma+1)/(gamma-1))^dims; the Hugoniot energy jump turns all the
+    kinetic energy into internal energy, e = u0^2 / 2."""
+
+    def __init__(self, gamma=5.0 / 3.0, u0=1.0, rho0=1.0, dims=3):
+        if dims not in (1, 2, 3):
+            raise ValueError("dims must be 1, 2 or 3")
+        self.g, self.u0, self.rho0, self.dims = gamma, u0, rho0, dims
+        self.D = u0 * (gamma - 1.0) / 2.0
+        self.rho_post = rho0 * ((gamma + 1.0) / (gamma - 1.0)) ** dims
+        self.e_post = 0.5 * u0 * u0
+
+    def shock_radius(self, t):
+        return self.D * t
+
+    def sample(self, r, t):
+        """(rho, u_r, p, e) at radii r (array, r > 0) and time t > 0."""
+        r = np.asarray(r, dtype=np.float64)
+        inside = r < self.D * t
+        rho = np.where(inside, self.rho_post, self.rho0 * (1.0 + self.u0 * t / r) ** (self.dims - 1))
+        u = np.where(inside, 0.0, -self.u0)
+        e = np.where(inside, self.e_post, 0.0)
+        p = (self.g - 1.0) * rho * e
+        return rho, u, p, e

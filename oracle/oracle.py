@@ -55,6 +55,8 @@ def lib():
         L.orc_init_sod.argtypes = [cfg] + [C.c_double] * 5 + [P] * 5
         L.orc_init_sedov.restype = C.c_int
         L.orc_init_sedov.argtypes = [cfg] + [C.c_double] * 3 + [P] * 5
+        L.orc_init_noh.restype = C.c_int
+        L.orc_init_noh.argtypes = [cfg] + [C.c_double] * 3 + [C.c_int] + [P] * 5
         L.orc_geometry.restype = C.c_int
         L.orc_geometry.argtypes = [cfg, C.c_void_p, P, P, P, P]
         L.orc_derived.restype = C.c_int
@@ -146,6 +148,15 @@ def sedov(g: Grid, rho0=1.0, p0=1e-6, edep=0.125) -> State:
                               _ptr(s.v), _ptr(s.w))
     if rc != OK:
         raise ValueError(f"orc_init_sedov: {rc}")
+    return s
+
+
+def noh(g: Grid, rho0=1.0, p0=0.0, u0=1.0, dims=3) -> State:
+    s = empty_state(g)
+    rc = lib().orc_init_noh(C.byref(g.c()), rho0, p0, u0, dims, _ptr(s.rho), _ptr(s.e), _ptr(s.u),
+                            _ptr(s.v), _ptr(s.w))
+    if rc != OK:
+        raise ValueError(f"orc_init_noh: {rc}")
     return s
 
 

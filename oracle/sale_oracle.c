@@ -888,6 +888,43 @@ int orc_init_sedov(const orc_config *g, double rho0, double p0, double edep, dou
   return ORC_OK;
 }
 
+/* Noh implosion (the shock problem of Noh, 1987, that Sec. I-D lists among
+ * the problems ScalSALE solves, in 1D, 2D or 3D): uniform rho0 with e = p0/((gamma-1) rho0) and every node
+ * moving toward the corner lo at speed u0 along the first `dims` axes
+ * (1 planar along x, 2 cylindrical about the z axis, 3 spherical): with
+ * r = (i dx, j dy, k dz) restricted to those axes, u_p = -u0 r/|r| (zero at
+ * r = 0). Wall-normal components are then zeroed on the six walls, as the
+ * reflective walls require; the walls through lo are symmetry planes of the
+ * problem, the others close the box. */
+int orc_init_noh(const orc_config *g, double rho0, double p0, double u0, int dims, double *rho,
+                 double *e, double *u, double *v, double *w) {
+  if (!config_valid(g) || dims < 1 || dims > 3) return ORC_EINVAL;
+  double dx, dy, dz;
+  spacing(g, &dx, &dy, &dz);
+  size_t nc = (size_t)NX * NY * NZ;
+  for (size_t c = 0; c < nc; c++) {
+    rho[c] = rho0;
+    e[c] = p0 / ((g->gamma - 1.0) * rho0);
+  }
+  for (int k = 0; k <= NZ; k++)
+    for (int j = 0; j <= NY; j++)
+      for (int i = 0; i <= NX; i++) {
+        double r[3] = {i * dx, dims >= 2 ? j * dy : 0.0, dims >= 3 ? k * dz : 0.0};
+        double len = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+        double vel[3] = {0.0, 0.0, 0.0};
+        if (len > 0.0)
+          for (int a = 0; a < 3; a++) vel[a] = -u0 * (r[a] / len);
+        if (i == 0 || i == NX) vel[0] = 0.0;
+        if (j == 0 || j == NY) vel[1] = 0.0;
+        if (k == 0 || k == NZ) vel[2] = 0.0;
+        size_t n = NI(g, i, j, k);
+        u[n] = vel[0];
+        v[n] = vel[1];
+        w[n] = vel[2];
+      }
+  return ORC_OK;
+}
+
 /* Run whole steps until t >= t_end or max_steps. Returns the last step's
  * code (ORC_DONE when t_end was reached); *steps counts completed steps. */
 int orc_run(const orc_config *g, orc_ws *W, double *rho, double *e, double *u, double *v,
