@@ -19,6 +19,9 @@ Also reported (one JSON line, extra keys):
                repeated runs (init, steps and the status read; launch bound).
   sedov128     Sedov 128^3 to t = 1.0, FP64: full-run latency and
                cell-updates/s.
+  noh128       spherical Noh implosion 128^3 to t = 0.6 (gamma 5/3, inflow
+               speed 1 toward the corner, p0 = 1e-6), FP64 and MIXED32:
+               full-run time, steps, cell-updates/s, peak density.
   batched      256 runs (seeded mix of Sod / Sedov, edges 16..64), MIXED32,
                200 steps each in ONE persistent launch: aggregate
                cell-updates/s, makespan, per-run latency p50/p99; the same
@@ -210,6 +213,31 @@ def sedov128(reps):
             "p50_s": pct(lat, 50), "cell_updates_per_s": 128 ** 3 * steps / pct(lat, 50), **out}
 
 
+def noh128(reps):
+    import torch
+    from paper_2209_01983_amd import sale
+
+    out = {"workload": "spherical noh 128^3 of [0,1]^3 to t=0.6, gamma 5/3"}
+    for name, prec in (("fp64", sale.SALE_FP64), ("mixed32", sale.SALE_MIXED32)):
+        cfg = sale.make_config(128, 128, 128, gamma=5.0 / 3.0, t_end=0.6, precision=prec)
+        lat, info = [], {}
+        for k in range(reps):
+            torch.cuda.synchronize()
+            a = time.perf_counter()
+            r = sale.SaleRun(cfg, sale.noh_problem(dims=3))
+            rc = r.run()
+            b = time.perf_counter()
+            if rc != sale.SALE_DONE:
+                raise RuntimeError(f"noh 128 run ended with {rc}")
+            if k == 0:
+                info = {"steps": r.state()[1], "peak_rho": float(r.fields(("rho",))["rho"].max())}
+            r.close()
+            lat.append(b - a)
+        out[name] = {"runs": reps, "p50_s": pct(lat, 50),
+                     "cell_updates_per_s": 128 ** 3 * info["steps"] / pct(lat, 50), **info}
+    return out
+
+
 def batched(seq_fp64=True):
     from paper_2209_01983_amd import sale, workloads
     from paper_2209_01983_amd.inputs import BATCH_SEED, batch_mix
@@ -392,6 +420,8 @@ def main():
         out["latency"] = sod_latency(50)
         say("sedov 128")
         out["sedov128"] = sedov128(3)
+        say("noh 128")
+        out["noh128"] = noh128(3)
         say("batched")
         out["batched"] = batched()
         out["serving"] = serving(a.serve_requests, a.serve_budget_gb)

@@ -69,6 +69,7 @@ extern "C" {
 #define SALE_SOD_X 0          /* Sod tube along x                        */
 #define SALE_SEDOV_CORNER 1   /* Sedov blast deposited in cell (0,0,0)   */
 #define SALE_USER 2           /* caller arrays                           */
+#define SALE_NOH 3            /* Noh implosion toward the corner lo      */
 
 /* status flag bits (sticky, see sale_status) */
 #define SALE_FLAG_TANGLE 1u   /* V* <= 0 or V^L <= 0                      */
@@ -109,11 +110,23 @@ typedef struct {
 } sale_config;
 
 typedef struct {
-  int32_t kind;             /* SALE_SOD_X | SALE_SEDOV_CORNER | SALE_USER   */
+  int32_t kind;             /* SALE_SOD_X | SALE_SEDOV_CORNER | SALE_USER |
+                               SALE_NOH                                     */
   double sod[5];            /* x_split, rho_L, p_L, rho_R, p_R (u = 0); a cell
                                is "left" iff its centre x < x_split          */
   double sedov[3];          /* rho0, p0, E_dep: uniform rho0, e = p0/((gamma-1)
                                rho0); cell (0,0,0) gets e = E_dep/(rho0 V0)  */
+  double noh[3];            /* rho0 > 0, p0 >= 0, u0: uniform rho0, e = p0/
+                               ((gamma-1) rho0), node velocity -u0 r/|r| with
+                               r = (i dx, j dy, k dz) restricted to the first
+                               noh_dims axes (0 at r = 0), wall-normal
+                               components zeroed on the walls. The Noh
+                               problem (Sec. I-D lists it among ScalSALE's
+                               problems) is cold (p0 = 0); a small p0 (e.g.
+                               1e-6) keeps e away from zero, where rounding
+                               in the kinetic-energy fix can make it
+                               negative (SALE_FLAG_NUMERIC)                 */
+  int32_t noh_dims;         /* 1 planar (x), 2 cylindrical (x, y), 3 spherical */
   const double *rho, *e;    /* SALE_USER: cells, logical layout             */
   const double *u, *v, *w;  /* SALE_USER: nodes, logical layout; wall-normal
                                components are set to zero on the walls      */

@@ -132,6 +132,11 @@ int validate_problem(const sale_problem *p, const Mesh &m) {
           !isfinite(p->sedov[2]) || !(p->sedov[2] >= 0.0))
         return SALE_EINVAL;
       return SALE_OK;
+    case SALE_NOH:
+      if (!finite_pos(p->noh[0]) || !isfinite(p->noh[1]) || !(p->noh[1] >= 0.0) || !isfinite(p->noh[2]) ||
+          p->noh_dims < 1 || p->noh_dims > 3)
+        return SALE_EINVAL;
+      return SALE_OK;
     case SALE_USER: {
       if (!p->rho || !p->e || !p->u || !p->v || !p->w) return SALE_EINVAL;
       if (p->user_on_device) return SALE_OK;  // checked on the device at init
@@ -154,6 +159,8 @@ hipError_t init_problem(const Mesh &m, Ctl *ctl, const Work<R> &w, const sale_pr
       return sale::launch_init_sod<R>(m, ctl, w, p->sod, p->t0, p->step0, t_end, s);
     case SALE_SEDOV_CORNER:
       return sale::launch_init_sedov<R>(m, ctl, w, p->sedov, p->t0, p->step0, t_end, s);
+    case SALE_NOH:
+      return sale::launch_init_noh<R>(m, ctl, w, p->noh, p->noh_dims, p->t0, p->step0, t_end, s);
     default: {
       const double *const src[5] = {p->rho, p->e, p->u, p->v, p->w};
       return sale::launch_init_user<R>(m, ctl, w, src, p->user_on_device != 0, p->t0, p->step0, t_end, s);

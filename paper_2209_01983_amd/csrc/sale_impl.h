@@ -149,6 +149,9 @@ hipError_t launch_init_sedov(const Mesh &m, Ctl *ctl, const Work<R> &w, const do
 // User arrays (double): copied through the scratch array into w.s[0], wall-
 // normal velocities zeroed, control block reset, first signal speed computed.
 template <typename R>
+hipError_t launch_init_noh(const Mesh &m, Ctl *ctl, const Work<R> &w, const double noh[3], int dims, double t0,
+                           long long step0, double t_end, hipStream_t s);
+template <typename R>
 hipError_t launch_init_user(const Mesh &m, Ctl *ctl, const Work<R> &w, const double *const src[5],
                             bool on_device, double t0, long long step0, double t_end, hipStream_t s);
 

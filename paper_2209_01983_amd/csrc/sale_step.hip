@@ -138,6 +138,38 @@ __global__ __launch_bounds__(TPB) void k_init_cells_sedov(Mesh m, State<R> s, do
   s.e[c] = R(c == 0 ? edep / (r0 * m.V0) : p0 / ((m.gamma - 1.0) * r0));
 }
 
+// Noh: uniform cells; node velocity -u0 r/|r| toward the corner lo over the
+// first `dims` axes, wall-normal components zeroed. Products and sums are
+// rounded one by one (no contraction into FMAs), so the initial state has the
+// bits of the plainly evaluated definition.
+template <typename R>
+__global__ __launch_bounds__(TPB) void k_init_cells_uniform(Mesh m, State<R> s, double r0, double p0) {
+  const int64_t c = blockIdx.x * (int64_t)TPB + threadIdx.x;
+  if (c >= m.ncell) return;
+  s.rho[c] = R(r0);
+  s.e[c] = R(p0 / ((m.gamma - 1.0) * r0));
+}
+
+template <typename R>
+__global__ __launch_bounds__(TPB) void k_init_nodes_noh(Mesh m, State<R> s, double u0, int dims) {
+#pragma clang fp contract(off)
+  const int64_t n = blockIdx.x * (int64_t)TPB + threadIdx.x;
+  if (n >= m.nnode) return;
+  int i, j, k;
+  node_ijk(m, n, i, j, k);
+  const double r[3] = {i * m.dx, dims >= 2 ? j * m.dy : 0.0, dims >= 3 ? k * m.dz : 0.0};
+  const double len = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+  double vel[3] = {0.0, 0.0, 0.0};
+  if (len > 0.0)
+    for (int a = 0; a < 3; a++) vel[a] = -u0 * (r[a] / len);
+  if (i == 0 || i == m.nx) vel[0] = 0.0;
+  if (j == 0 || j == m.ny) vel[1] = 0.0;
+  if (k == 0 || k == m.nz) vel[2] = 0.0;
+  s.u[n] = R(vel[0]);
+  s.v[n] = R(vel[1]);
+  s.w[n] = R(vel[2]);
+}
+
 template <typename R>
 __global__ __launch_bounds__(TPB) void k_zero_nodes(Mesh m, State<R> s) {
   const int64_t n = blockIdx.x * (int64_t)TPB + threadIdx.x;
@@ -400,6 +432,14 @@ hipError_t launch_init_sedov(const Mesh &m, Ctl *ctl, const Work<R> &w, const do
 }
 
 template <typename R>
+hipError_t launch_init_noh(const Mesh &m, Ctl *ctl, const Work<R> &w, const double noh[3], int dims, double t0,
+                           long long step0, double t_end, hipStream_t s) {
+  hipLaunchKernelGGL(k_init_cells_uniform<R>, dim3(blocks(m.ncell)), dim3(TPB), 0, s, m, w.s[0], noh[0], noh[1]);
+  hipLaunchKernelGGL(k_init_nodes_noh<R>, dim3(blocks(m.nnode)), dim3(TPB), 0, s, m, w.s[0], noh[2], dims);
+  return finish_init(m, ctl, w, t0, step0, t_end, s);
+}
+
+template <typename R>
 hipError_t launch_init_user(const Mesh &m, Ctl *ctl, const Work<R> &w, const double *const src[5],
                             bool on_device, double t0, long long step0, double t_end, hipStream_t s) {
   R *dst[5] = {w.s[0].rho, w.s[0].e, w.s[0].u, w.s[0].v, w.s[0].w};
@@ -502,6 +542,8 @@ hipError_t launch_export(const Mesh &m, const Work<R> &w, int cur, int which, do
                                          long long, double, hipStream_t);                                \
   template hipError_t launch_init_sedov<R>(const Mesh &, Ctl *, const Work<R> &, const double[3], double, \
                                            long long, double, hipStream_t);                              \
+  template hipError_t launch_init_noh<R>(const Mesh &, Ctl *, const Work<R> &, const double[3], int, double,    \
+                                         long long, double, hipStream_t);                                       \
   template hipError_t launch_init_user<R>(const Mesh &, Ctl *, const Work<R> &, const double *const[5],  \
                                           bool, double, long long, double, hipStream_t);                 \
   template RunArgs<R> run_args<R>(const Mesh &, Ctl *, const Work<R> &, int, const Launch &);            \

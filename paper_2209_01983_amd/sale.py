@@ -24,7 +24,7 @@ SALE_OK, SALE_DONE = 0, 1
 SALE_EINVAL, SALE_ENOMEM, SALE_EHIP, SALE_ENUMERIC, SALE_ETANGLE, SALE_EBUSY = -1, -2, -3, -4, -5, -6
 SALE_FP64, SALE_MIXED32 = 0, 1
 SALE_BC_REFLECT = 0
-SALE_SOD_X, SALE_SEDOV_CORNER, SALE_USER = 0, 1, 2
+SALE_SOD_X, SALE_SEDOV_CORNER, SALE_USER, SALE_NOH = 0, 1, 2, 3
 SALE_FLAG_TANGLE, SALE_FLAG_NUMERIC = 1, 2
 SALE_F_RHO, SALE_F_E, SALE_F_P, SALE_F_Q = 1 << 0, 1 << 1, 1 << 2, 1 << 3
 SALE_F_U, SALE_F_V, SALE_F_W = 1 << 4, 1 << 5, 1 << 6
@@ -53,7 +53,7 @@ class sale_config(C.Structure):
 
 class sale_problem(C.Structure):
     _fields_ = [("kind", C.c_int32), ("sod", C.c_double * 5), ("sedov", C.c_double * 3),
-                ("rho", C.c_void_p), ("e", C.c_void_p), ("u", C.c_void_p), ("v", C.c_void_p),
+                ("noh", C.c_double * 3), ("noh_dims", C.c_int32), ("rho", C.c_void_p), ("e", C.c_void_p), ("u", C.c_void_p), ("v", C.c_void_p),
                 ("w", C.c_void_p), ("user_on_device", C.c_int32), ("t0", C.c_double),
                 ("step0", C.c_int64)]
 
@@ -232,6 +232,16 @@ def sedov_problem(rho0=1.0, p0=1e-6, edep=0.125, t0=0.0, step0=0) -> sale_proble
     p = sale_problem()
     p.kind = SALE_SEDOV_CORNER
     p.sedov = (C.c_double * 3)(rho0, p0, edep)
+    p.t0, p.step0 = t0, step0
+    return p
+
+
+def noh_problem(rho0=1.0, p0=1e-6, u0=1.0, dims=3, t0=0.0, step0=0) -> sale_problem:
+    """Noh implosion toward the corner lo (use gamma = 5/3 in the config)."""
+    p = sale_problem()
+    p.kind = SALE_NOH
+    p.noh = (C.c_double * 3)(rho0, p0, u0)
+    p.noh_dims = dims
     p.t0, p.step0 = t0, step0
     return p
 

@@ -4,6 +4,7 @@ validation before touching a device (no compute calls here)."""
 import ctypes as C
 import os
 import re
+import subprocess
 
 import numpy as np
 import pytest
@@ -29,10 +30,26 @@ def test_library_exports_every_declared_function():
     assert set(decl) == set(sale.EXPORTS) | set(sale.POOL_EXPORTS)
 
 
-def test_struct_layout_matches_header_sizes():
-    # int32 x3, pad, 6 doubles, 5 doubles, int32, int32[6], int32 remap order
-    assert C.sizeof(sale.sale_config) == 12 + 4 + 48 + 40 + 4 + 24 + 4
-    assert C.sizeof(sale.sale_problem) == 8 + 40 + 24 + 40 + 8 + 8 + 8
+def test_struct_layout_matches_header(tmp_path):
+    """Size and every field offset of the ctypes mirrors equal what a C
+    compiler makes of include/sale.h."""
+    structs = {"sale_config": sale.sale_config, "sale_problem": sale.sale_problem}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', "int main(void) {"]
+    for name, cls in structs.items():
+        lines.append(f'  printf("{name} size %zu\\n", sizeof({name}));')
+        for f, _ in cls._fields_:
+            lines.append(f'  printf("{name} {f} %zu\\n", offsetof({name}, {f}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-o", str(exe), str(src)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for name, cls in structs.items():
+        assert got[(name, "size")] == C.sizeof(cls), name
+        for f, _ in cls._fields_:
+            assert got[(name, f)] == getattr(cls, f).offset, (name, f)
 
 
 @pytest.mark.parametrize("bad", [
@@ -72,6 +89,11 @@ def test_invalid_problems_rejected_before_device_work():
     assert sale.sale_init(cfg, bad_sod, 256, 1 << 30, 0)[0] == sale.SALE_EINVAL
     bad_sedov = sale.sedov_problem(edep=float("nan"))
     assert sale.sale_init(cfg, bad_sedov, 256, 1 << 30, 0)[0] == sale.SALE_EINVAL
+    for kw in (dict(rho0=0.0), dict(p0=-1e-9), dict(u0=float("nan")), dict(dims=0), dict(dims=4)):
+        assert sale.sale_init(cfg, sale.noh_problem(**kw), 256, 1 << 30, 0)[0] == sale.SALE_EINVAL, kw
+    bad_kind = sale.sedov_problem()
+    bad_kind.kind = 4
+    assert sale.sale_init(cfg, bad_kind, 256, 1 << 30, 0)[0] == sale.SALE_EINVAL
     # misaligned or missing workspace, too small workspace
     ok = sale.sedov_problem()
     assert sale.sale_init(cfg, ok, 0, 1 << 30, 0)[0] == sale.SALE_EINVAL
