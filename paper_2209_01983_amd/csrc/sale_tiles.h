@@ -47,6 +47,19 @@ __device__ __forceinline__ T &plane_at(T *base, int64_t plane, int k, uint32_t o
       typename std::conditional<std::is_const<T>::value, const char, char>::type *>(base) + (uint64_t)b);
 }
 
+// A prefetched value is settled here: the wait for its load is taken at this
+// point, and later uses see a value produced by the (empty) statement, so
+// they wait for nothing. The hardware counts loads and stores in one counter
+// and the compiler, across branches, can only wait for all of them at once:
+// a value used first at the top of the next plane would drain that plane's
+// stores as well, and one loaded before the loop would drain the loads just
+// issued. Settling a plane's prefetch after its longest phase and before its
+// stores keeps both off the critical path.
+template <typename T>
+__device__ __forceinline__ void settle(T &x) {
+  asm volatile("" : "+v"(x));
+}
+
 // ---- O5: acoustic predictor P* of one cell (O2, O4 folded in) ----------------
 // Divisions by a quantity used more than once go through one reciprocal
 // (rounding-level differences from the oracle's divisions).
@@ -197,6 +210,7 @@ __device__ bool lagrange_tile(const RunArgs<R> &a, int b, double dtd, double *ld
     }
   };
   fetch(Z0 - 2);
+  settle(fu), settle(fv), settle(fw), settle(frho), settle(fe);
 
   for (int k = Z0 - 2; k <= Z1; k++) {
     // ---- P1 ----
@@ -320,6 +334,7 @@ __device__ bool lagrange_tile(const RunArgs<R> &a, int b, double dtd, double *ld
       sVY[cj][ci] = vy;
     }
     __syncthreads();
+    settle(fu), settle(fv), settle(fw), settle(frho), settle(fe);  // loads issued in P1
     // ---- P5: V^L, rho^L, e^L of cell plane k-1 ----
     if (own_cell && plane_ok && cp >= Z0 && cp < Z1) {
       const double VL =
@@ -438,6 +453,8 @@ __device__ void remap_tile(const RunArgs<R> &a, int b, double *lds, double *amax
   // the u' ring starts empty (node planes below Z0-2 only feed non-owned results)
   for (int q = threadIdx.x; q < 3 * 3 * CH * CW; q += NTH) (&UPR[0][0][0][0])[q] = R(0);
   fetch(Z0 - 2);
+  settle(f_rl), settle(f_el), settle(f_rho), settle(f_u), settle(f_v), settle(f_w);
+  settle(f_vx), settle(f_vy), settle(f_vz);
   __syncthreads();
 
   for (int c = Z0 - 3; c <= Z1; c++) {  // c >= -3
@@ -554,6 +571,8 @@ __device__ void remap_tile(const RunArgs<R> &a, int b, double *lds, double *amax
       pr_c1 = pr;
     }
     __syncthreads();
+    settle(f_rl), settle(f_el), settle(f_rho), settle(f_u), settle(f_v), settle(f_w);  // loads issued in P1
+    settle(f_vx), settle(f_vy), settle(f_vz);
     // ---- P5: node plane c --------------------------------------------------------------
     {
       R un = 0, vn = 0, wn = 0, sp = 0, dk = 0;
