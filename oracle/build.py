@@ -1,4 +1,6 @@
-"""Build the plain-C FP64 oracle into ``oracle/liboracle.so`` with gcc.
+"""Build the plain-C FP64 oracle (the Eulerian step in ``sale_oracle.c``, the
+pure-Lagrangian step in ``lagrange_oracle.c``) into ``oracle/liboracle.so``
+with gcc.
 
 Test infrastructure: the oracle is the checker of the HIP path, never a part
 of it. Flags: no fast-math and no FP contraction, so every operation rounds
@@ -9,6 +11,7 @@ import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "sale_oracle.c")
+SRC_LAG = os.path.join(HERE, "lagrange_oracle.c")
 LIB = os.path.join(HERE, "liboracle.so")
 
 CFLAGS = ["-O3", "-fno-fast-math", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared",
@@ -18,7 +21,7 @@ CFLAGS = ["-O3", "-fno-fast-math", "-ffp-contract=off", "-fopenmp", "-fPIC", "-s
 def build_oracle(verbose: bool = False) -> str:
     """Compile the oracle (always; it takes about a second) and return the path."""
     tmp = LIB + ".tmp"
-    cmd = ["gcc", *CFLAGS, "-o", tmp, SRC, "-lm"]
+    cmd = ["gcc", *CFLAGS, "-o", tmp, SRC, SRC_LAG, "-lm"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
