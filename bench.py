@@ -22,6 +22,9 @@ Also reported (one JSON line, extra keys):
   noh128       spherical Noh implosion 128^3 to t = 0.6 (gamma 5/3, inflow
                speed 1 toward the corner, p0 = 1e-6), FP64 and MIXED32:
                full-run time, steps, cell-updates/s, peak density.
+  lagrange128  pure-Lagrangian mode (the mesh moves with the flow), Sedov
+               128^3, FP64: per-step throughput over a 100-step window after
+               10 warm-up steps, kernel split (forces+nodes, energy+geometry).
   batched      256 runs (seeded mix of Sod / Sedov, edges 16..64), MIXED32,
                200 steps each in ONE persistent launch: aggregate
                cell-updates/s, makespan, per-run latency p50/p99; the same
@@ -238,6 +241,26 @@ def noh128(reps):
     return out
 
 
+def lagrange128(steps=100, warmup=10):
+    import torch
+    from paper_2209_01983_amd import sale
+
+    n = 128
+    cfg = sale.make_config(n, n, n, hi=(1.2, 1.2, 1.2), t_end=1.0, mode=sale.SALE_LAGRANGIAN, c_hg=0.1)
+    r = sale.SaleRun(cfg, sale.sedov_problem())
+    r.step(warmup)
+    torch.cuda.synchronize()
+    ms = r.step_timed(steps)
+    t, nstep, _, flags = r.state()
+    if flags:
+        raise RuntimeError(f"lagrangian sedov flags {flags}")
+    per = sum(ms) / steps
+    return {"workload": "sedov 128^3 pure Lagrangian (moving mesh), fp64, hourglass 0.1",
+            "steps": steps, "ms_per_step": per, "cell_updates_per_s": n ** 3 * 1e3 / per,
+            "kernel_ms": {"begin": ms[0] / steps, "forces+nodes": ms[1] / steps, "energy+geometry": ms[2] / steps},
+            "sim_time_end_of_window": t}
+
+
 def batched(seq_fp64=True):
     from paper_2209_01983_amd import sale, workloads
     from paper_2209_01983_amd.inputs import BATCH_SEED, batch_mix
@@ -422,6 +445,8 @@ def main():
         out["sedov128"] = sedov128(3)
         say("noh 128")
         out["noh128"] = noh128(3)
+        say("lagrange 128")
+        out["lagrange128"] = lagrange128()
         say("batched")
         out["batched"] = batched()
         out["serving"] = serving(a.serve_requests, a.serve_budget_gb)

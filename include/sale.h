@@ -66,6 +66,9 @@ extern "C" {
                              as FP32)                                     */
 #define SALE_BC_REFLECT 0 /* reflective (slip) wall                      */
 
+#define SALE_EULERIAN 0   /* Lagrangian phase + remap to the fixed mesh  */
+#define SALE_LAGRANGIAN 1 /* pure Lagrangian: the mesh moves with the flow */
+
 #define SALE_SOD_X 0          /* Sod tube along x                        */
 #define SALE_SEDOV_CORNER 1   /* Sedov blast deposited in cell (0,0,0)   */
 #define SALE_USER 2           /* caller arrays                           */
@@ -88,6 +91,10 @@ extern "C" {
 #define SALE_F_CLOCK (1u << 9)  /* host double[2]: device wall clock (s) at the
                                    run's first pool advance and when its last
                                    step completed in a pool (0: never)     */
+#define SALE_F_X (1u << 10)     /* nodes: x position (the moving mesh in the
+                                   pure-Lagrangian mode, else the fixed one) */
+#define SALE_F_Y (1u << 11)     /* nodes: y position                        */
+#define SALE_F_Z (1u << 12)     /* nodes: z position                        */
 
 /* ---- configuration ----------------------------------------------------- */
 typedef struct {
@@ -107,6 +114,19 @@ typedef struct {
                                swept volume's centroid (van Leer slopes),
                                cells and dual mesh; single runs only (a
                                pool admits order 1)                         */
+  int32_t mode;             /* SALE_EULERIAN (default) | SALE_LAGRANGIAN: the
+                               paper's Lagrangian rezoning (Table I, Fig. 2a),
+                               the mesh moves with the flow and is never
+                               remapped. The Lagrangian mode: FP64 only,
+                               single runs only (a pool admits SALE_EULERIAN),
+                               remap_order ignored (must be <= 1), starts from
+                               the Cartesian mesh of lo/hi (any problem kind),
+                               per-cell length scale V / largest face area,
+                               exact trilinear-hex volumes and corner vectors,
+                               SALE_F_Q not available                        */
+  double c_hg;              /* viscous hourglass coefficient >= 0 of the
+                               Lagrangian mode (Flanagan-Belytschko form;
+                               0 disables; e.g. 0.1)                        */
 } sale_config;
 
 typedef struct {

@@ -74,6 +74,9 @@ int validate_config(const sale_config *c) {
   for (int a = 0; a < 6; a++)
     if (c->bc[a] != SALE_BC_REFLECT) return SALE_EINVAL;
   if (c->remap_order < 0 || c->remap_order > 2) return SALE_EINVAL;
+  if (c->mode != SALE_EULERIAN && c->mode != SALE_LAGRANGIAN) return SALE_EINVAL;
+  if (!isfinite(c->c_hg) || !(c->c_hg >= 0.0)) return SALE_EINVAL;
+  if (c->mode == SALE_LAGRANGIAN && (c->precision != SALE_FP64 || c->remap_order > 1)) return SALE_EINVAL;
   // the step kernels address each field array with 32-bit byte offsets
   const int64_t nnode = (int64_t)(c->nx + 1) * (c->ny + 1) * (c->nz + 1);
   if (nnode * (int64_t)sizeof(double) >= ((int64_t)1 << 32)) return SALE_EINVAL;
@@ -110,6 +113,8 @@ Mesh make_mesh(const sale_config *c) {
   m.hdz = 0.5 * m.dz;
   m.ncell = (int64_t)c->nx * c->ny * c->nz;
   m.order = c->remap_order == 2 ? 2 : 1;
+  m.mode = c->mode == SALE_LAGRANGIAN ? 1 : 0;
+  m.chg = c->c_hg;
   m.nnode = (int64_t)(c->nx + 1) * (c->ny + 1) * (c->nz + 1);
   return m;
 }
@@ -184,7 +189,8 @@ double next_dt(const Ctl &c, const Mesh &m) {
   double amax = 0.0;
   memcpy(&amax, &c.amax_bits, sizeof(amax));
   const double rem = c.t_end - c.t;
-  double dt = amax > 0.0 ? m.cfl * m.h / amax : rem;
+  // the Lagrangian mode keeps the largest a / h of its cells, not of a
+  double dt = amax > 0.0 ? (m.mode == 1 ? m.cfl / amax : m.cfl * m.h / amax) : rem;
   return dt > rem ? rem : dt;
 }
 
@@ -249,7 +255,8 @@ int fields_impl(const Mesh &m, int precision, const Work<double> &w64, const Wor
                 Ctl *ctl, hipStream_t stream, uint32_t mask, void *const *dst, int dst_on_device,
                 int as_fp64) {
   if (mask && !dst) return SALE_EINVAL;
-  if (mask & ~((SALE_F_CLOCK << 1) - 1u)) return SALE_EINVAL;
+  if (mask & ~((SALE_F_Z << 1) - 1u)) return SALE_EINVAL;
+  if ((mask & SALE_F_Q) && m.mode == 1) return SALE_EINVAL;
   const hipMemcpyKind kind = dst_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
   const bool fp64 = precision == SALE_FP64;
   double *scratch = fp64 ? w64.scratch : w32.scratch;
@@ -259,7 +266,7 @@ int fields_impl(const Mesh &m, int precision, const Work<double> &w64, const Wor
     if (e_ != hipSuccess) return hip_fail(e_, #expr); \
   } while (0)
   int slot = 0;
-  for (uint32_t bit = 1; bit <= SALE_F_CLOCK; bit <<= 1) {
+  for (uint32_t bit = 1; bit <= SALE_F_Z; bit <<= 1) {
     if (!(mask & bit)) continue;
     void *d = dst[slot++];
     if (!d) return SALE_EINVAL;
@@ -315,6 +322,12 @@ int fields_impl(const Mesh &m, int precision, const Work<double> &w64, const Wor
       if (rc != SALE_OK) return rc;
       ((double *)d)[0] = c.totals[0];
       ((double *)d)[1] = c.totals[1];
+    } else if (bit == SALE_F_X || bit == SALE_F_Y || bit == SALE_F_Z) {
+      const int axis = bit == SALE_F_X ? 0 : bit == SALE_F_Y ? 1 : 2;
+      HIP_TRY_F(fp64 ? sale::launch_positions<double>(m, w64, cur, axis, scratch, stream)
+                     : sale::launch_positions<float>(m, w32, cur, axis, scratch, stream));
+      HIP_TRY_F(hipMemcpyAsync(d, scratch, (size_t)m.nnode * sizeof(double), kind, stream));
+      HIP_TRY_F(hipStreamSynchronize(stream));  // the scratch array is reused next
     } else if (bit == SALE_F_CLOCK) {
       Ctl c;
       int rc = read_ctl(stream, ctl, &c);
@@ -376,6 +389,7 @@ int sale_init(const sale_config *cfg, const sale_problem *prob, void *d_ws, size
   if (x->precision == SALE_FP64) {
     sale::layout<double>(m, d_ws, &x->ctl, &x->w64);
     e = init_problem<double>(m, x->ctl, x->w64, prob, x->t_end, x->stream);
+    if (e == hipSuccess && m.mode == 1) e = sale::launch_lag_init(m, x->ctl, x->w64, x->stream);
   } else {
     sale::layout<float>(m, d_ws, &x->ctl, &x->w32);
     e = init_problem<float>(m, x->ctl, x->w32, prob, x->t_end, x->stream);
@@ -612,7 +626,7 @@ int sale_pool_admit(sale_pool *p, const sale_config *cfg, const sale_problem *pr
   if (rc != SALE_OK) return rc;
   if (cfg->precision != p->precision) return SALE_EINVAL;
   const Mesh m = make_mesh(cfg);
-  if (m.order != 1) return SALE_EINVAL;  // the persistent kernel remaps to first order
+  if (m.order != 1 || m.mode != 0) return SALE_EINVAL;  // the persistent kernel: Eulerian, first order
   if ((rc = validate_problem(prob, m)) != SALE_OK) return rc;
   int s = -1;
   for (int k = 0; k < p->max_runs; k++)

@@ -56,6 +56,16 @@ __device__ __forceinline__ R swept_volume(const R d0[3], const R d1[3], const R 
   return t0 + hh1 * i1 + hh2 * i2 + third * trip;
 }
 
+// a * b rounded on its own: the empty statement hides the product from the
+// compiler, which would otherwise fuse it with a following add (the build
+// contracts across statements, and a per-function pragma does not stop the
+// code generator from doing so)
+__device__ __forceinline__ double mul_rn(double a, double b) {
+  double p = a * b;
+  asm volatile("" : "+v"(p));
+  return p;
+}
+
 // Cell divergence D = (1/V0) sum_p S_cp . u_p from the halves of its corner
 // sums on the cell's lower (a) and upper (b) node planes: x and y halves are
 // pairwise edge differences, z halves the sums of w over the plane's four

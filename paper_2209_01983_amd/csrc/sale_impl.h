@@ -26,6 +26,8 @@ struct Mesh {
   double hdx, hdy, hdz;      // half spacings dx/2, dy/2, dz/2
   int64_t ncell, nnode;
   int order;                 // remap order: 1 donor cell, 2 limited linear
+  int mode;                  // 0 Eulerian (Lagrange + remap), 1 pure Lagrangian (mesh moves)
+  double chg;                // hourglass viscosity coefficient (pure Lagrangian mode)
 };
 
 // Device control block (one per run). `done` is decided once per step by the
@@ -85,6 +87,16 @@ struct Rem2 {
   R *dk;
 };
 
+// Pure-Lagrangian mode (FP64 only; null otherwise): node positions of the two
+// states, the constant cell masses, and the corner forces of the step in
+// flight, F[(3 a + d) * ncell + c] for corner a = (a&1, a>>1&1, a>>2&1) and
+// component d of cell c.
+struct Lag {
+  double *x[2], *y[2], *z[2];
+  double *m;
+  double *F;
+};
+
 template <typename R>
 struct Work {
   State<R> s[2];
@@ -93,7 +105,19 @@ struct Work {
   double *partial;
   double *scratch;
   Rem2<R> r2;
+  Lag lg;
 };
+
+// Pure-Lagrangian mode: positions and masses of the initial Cartesian mesh
+// from state w.s[0] and the first signal (max over cells of a / h) into ctl;
+// one step from buffer cur into 1 - cur (kernels in sale_lagrange.hip).
+hipError_t launch_lag_init(const Mesh &m, Ctl *ctl, const Work<double> &w, hipStream_t s);
+hipError_t launch_lag_step(const Mesh &m, Ctl *ctl, const Work<double> &w, int cur, hipStream_t s,
+                           const hipEvent_t *ev);
+// Node coordinate `axis` of state buffer `cur` as doubles into out: the
+// moving mesh in the pure-Lagrangian mode, the fixed mesh otherwise.
+template <typename R>
+hipError_t launch_positions(const Mesh &m, const Work<R> &w, int cur, int axis, double *out, hipStream_t s);
 
 // The second-order remap (multi-pass kernels in sale_remap2.hip): from the
 // Lagrangian results in w.geo / u' into w.s[1 - cur], then the next signal

@@ -139,9 +139,8 @@ __global__ __launch_bounds__(TPB) void k_init_cells_sedov(Mesh m, State<R> s, do
 }
 
 // Noh: uniform cells; node velocity -u0 r/|r| toward the corner lo over the
-// first `dims` axes, wall-normal components zeroed. Products and sums are
-// rounded one by one (no contraction into FMAs), so the initial state has the
-// bits of the plainly evaluated definition.
+// first `dims` axes, wall-normal components zeroed. Products are rounded on
+// their own (not fused into the sums), as the definition is written.
 template <typename R>
 __global__ __launch_bounds__(TPB) void k_init_cells_uniform(Mesh m, State<R> s, double r0, double p0) {
   const int64_t c = blockIdx.x * (int64_t)TPB + threadIdx.x;
@@ -152,13 +151,12 @@ __global__ __launch_bounds__(TPB) void k_init_cells_uniform(Mesh m, State<R> s, 
 
 template <typename R>
 __global__ __launch_bounds__(TPB) void k_init_nodes_noh(Mesh m, State<R> s, double u0, int dims) {
-#pragma clang fp contract(off)
   const int64_t n = blockIdx.x * (int64_t)TPB + threadIdx.x;
   if (n >= m.nnode) return;
   int i, j, k;
   node_ijk(m, n, i, j, k);
-  const double r[3] = {i * m.dx, dims >= 2 ? j * m.dy : 0.0, dims >= 3 ? k * m.dz : 0.0};
-  const double len = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+  const double r[3] = {mul_rn(i, m.dx), dims >= 2 ? mul_rn(j, m.dy) : 0.0, dims >= 3 ? mul_rn(k, m.dz) : 0.0};
+  const double len = sqrt((mul_rn(r[0], r[0]) + mul_rn(r[1], r[1])) + mul_rn(r[2], r[2]));
   double vel[3] = {0.0, 0.0, 0.0};
   if (len > 0.0)
     for (int a = 0; a < 3; a++) vel[a] = -u0 * (r[a] / len);
@@ -213,6 +211,42 @@ __global__ __launch_bounds__(TPB) void k_totals_partial(Mesh m, State<R> s, doub
       for (int b = -1; b <= 0; b++)
         for (int a = -1; a <= 0; a++)
           if (cell_in(m, i + a, j + b, k + cc)) ms += (double)s.rho[cidx(m, i + a, j + b, k + cc)] * m.V0;
+    const double u = s.u[n], v = s.v[n], w = s.w[n];
+    sk += 0.5 * (0.125 * ms) * (u * u + v * v + w * w);
+  }
+  __shared__ double red[3][TPB / 64];
+  sm = wave_sum(sm);
+  si = wave_sum(si);
+  sk = wave_sum(sk);
+  if ((threadIdx.x & 63) == 0) {
+    red[0][threadIdx.x >> 6] = sm;
+    red[1][threadIdx.x >> 6] = si;
+    red[2][threadIdx.x >> 6] = sk;
+  }
+  __syncthreads();
+  if (threadIdx.x < 3) {
+    double r = 0.0;
+    for (int q = 0; q < TPB / 64; q++) r += red[threadIdx.x][q];
+    partial[threadIdx.x * TOT_BLOCKS + blockIdx.x] = r;
+  }
+}
+
+// pure-Lagrangian mode: cell masses are stored (constant), not rho V0
+__global__ __launch_bounds__(TPB) void k_lag_totals_partial(Mesh m, State<double> s, const double *mass,
+                                                            double *partial) {
+  double sm = 0.0, si = 0.0, sk = 0.0;
+  for (int64_t c = blockIdx.x * (int64_t)TPB + threadIdx.x; c < m.ncell; c += (int64_t)TOT_BLOCKS * TPB) {
+    sm += mass[c];
+    si += mass[c] * s.e[c];
+  }
+  for (int64_t n = blockIdx.x * (int64_t)TPB + threadIdx.x; n < m.nnode; n += (int64_t)TOT_BLOCKS * TPB) {
+    int i, j, k;
+    node_ijk(m, n, i, j, k);
+    double ms = 0.0;
+    for (int cc = -1; cc <= 0; cc++)
+      for (int b = -1; b <= 0; b++)
+        for (int a = -1; a <= 0; a++)
+          if (cell_in(m, i + a, j + b, k + cc)) ms += mass[cidx(m, i + a, j + b, k + cc)];
     const double u = s.u[n], v = s.v[n], w = s.w[n];
     sk += 0.5 * (0.125 * ms) * (u * u + v * v + w * w);
   }
@@ -356,8 +390,10 @@ size_t workspace_bytes(const Mesh &m) {
   const size_t sD = align256((size_t)(m.ncell > m.nnode ? m.ncell : m.nnode) * sizeof(double));
   // ctl | 2 states | u' | rho^L, e^L | 3 swept volumes | partials | scratch
   const size_t r2 = m.order == 2 ? 8 * cR + nR : 0;  // second-order remap intermediates
+  const size_t cD = align256((size_t)m.ncell * sizeof(double)), nD = align256((size_t)m.nnode * sizeof(double));
+  const size_t lg = m.mode == 1 ? 6 * nD + 25 * cD : 0;  // positions x2, masses, corner forces
   return align256(sizeof(Ctl)) + 2 * (2 * cR + 3 * nR) + 3 * nR + 2 * cR + 3 * cR +
-         align256(3 * TOT_BLOCKS * sizeof(double)) + sD + r2;
+         align256(3 * TOT_BLOCKS * sizeof(double)) + sD + r2 + lg;
 }
 
 template <typename R>
@@ -401,6 +437,17 @@ void layout(const Mesh &m, void *ws, Ctl **ctl, Work<R> *w) {
     w->r2.M = takeR(cR);
     w->r2.epre = takeR(cR);
     w->r2.dk = takeR(nR);
+  }
+  w->lg = Lag{};
+  if (m.mode == 1) {
+    const size_t cD = align256((size_t)m.ncell * sizeof(double)), nD = align256((size_t)m.nnode * sizeof(double));
+    for (int a = 0; a < 2; a++) {
+      w->lg.x[a] = takeD(nD);
+      w->lg.y[a] = takeD(nD);
+      w->lg.z[a] = takeD(nD);
+    }
+    w->lg.m = takeD(cD);
+    w->lg.F = takeD(24 * cD);
   }
 }
 
@@ -491,6 +538,12 @@ template <typename R>
 hipError_t launch_step(const Mesh &m, Ctl *ctl, const Work<R> &w, int cur, const Launch &L, hipStream_t s,
                        const hipEvent_t *ev) {
   if (!launch_valid(L)) return hipErrorInvalidValue;
+  if (m.mode == 1) {  // pure Lagrangian (FP64 only; the API refuses other precisions)
+    if constexpr (std::is_same<R, double>::value)
+      return launch_lag_step(m, ctl, w, cur, s, ev);
+    else
+      return hipErrorInvalidValue;
+  }
   const RunArgs<R> a = run_args<R>(m, ctl, w, cur, L);
   hipError_t e = hipSuccess;
   if (ev) e = hipEventRecord(ev[0], s);
@@ -523,7 +576,15 @@ hipError_t launch_step(const Mesh &m, Ctl *ctl, const Work<R> &w, int cur, const
 
 template <typename R>
 hipError_t launch_totals(const Mesh &m, Ctl *ctl, const Work<R> &w, int cur, hipStream_t s) {
-  hipLaunchKernelGGL(k_totals_partial<R>, dim3(TOT_BLOCKS), dim3(TPB), 0, s, m, w.s[cur], w.partial);
+  if constexpr (std::is_same<R, double>::value) {
+    if (m.mode == 1)
+      hipLaunchKernelGGL(k_lag_totals_partial, dim3(TOT_BLOCKS), dim3(TPB), 0, s, m, w.s[cur],
+                         (const double *)w.lg.m, w.partial);
+    else
+      hipLaunchKernelGGL(k_totals_partial<R>, dim3(TOT_BLOCKS), dim3(TPB), 0, s, m, w.s[cur], w.partial);
+  } else {
+    hipLaunchKernelGGL(k_totals_partial<R>, dim3(TOT_BLOCKS), dim3(TPB), 0, s, m, w.s[cur], w.partial);
+  }
   hipLaunchKernelGGL(k_totals_final, dim3(1), dim3(TPB), 0, s, ctl, (const double *)w.partial);
   return hipGetLastError();
 }

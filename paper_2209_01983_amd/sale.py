@@ -29,11 +29,13 @@ SALE_FLAG_TANGLE, SALE_FLAG_NUMERIC = 1, 2
 SALE_F_RHO, SALE_F_E, SALE_F_P, SALE_F_Q = 1 << 0, 1 << 1, 1 << 2, 1 << 3
 SALE_F_U, SALE_F_V, SALE_F_W = 1 << 4, 1 << 5, 1 << 6
 SALE_F_STATE, SALE_F_TOTALS, SALE_F_CLOCK = 1 << 7, 1 << 8, 1 << 9
+SALE_F_X, SALE_F_Y, SALE_F_Z = 1 << 10, 1 << 11, 1 << 12
+SALE_EULERIAN, SALE_LAGRANGIAN = 0, 1
 
 FIELD_BITS = {"rho": SALE_F_RHO, "e": SALE_F_E, "p": SALE_F_P, "q": SALE_F_Q,
-              "u": SALE_F_U, "v": SALE_F_V, "w": SALE_F_W}
+              "u": SALE_F_U, "v": SALE_F_V, "w": SALE_F_W, "x": SALE_F_X, "y": SALE_F_Y, "z": SALE_F_Z}
 CELL_FIELDS = ("rho", "e", "p", "q")
-NODE_FIELDS = ("u", "v", "w")
+NODE_FIELDS = ("u", "v", "w", "x", "y", "z")
 
 # functions the header declares (checked by the tests against include/sale.h)
 EXPORTS = ("sale_workspace_bytes", "sale_init", "sale_step", "sale_run", "sale_fields",
@@ -48,7 +50,7 @@ class sale_config(C.Structure):
                 ("gamma", C.c_double), ("cfl", C.c_double),
                 ("c_quad", C.c_double), ("c_lin", C.c_double),
                 ("t_end", C.c_double), ("precision", C.c_int32), ("bc", C.c_int32 * 6),
-                ("remap_order", C.c_int32)]
+                ("remap_order", C.c_int32), ("mode", C.c_int32), ("c_hg", C.c_double)]
 
 
 class sale_problem(C.Structure):
@@ -215,9 +217,11 @@ def sale_pool_destroy(pool) -> None:
 
 # ---- helpers ------------------------------------------------------------------------
 def make_config(nx, ny, nz, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), gamma=1.4, cfl=0.5,
-                c_quad=1.0, c_lin=0.5, t_end=1.0, precision=SALE_FP64, remap_order=1) -> sale_config:
+                c_quad=1.0, c_lin=0.5, t_end=1.0, precision=SALE_FP64, remap_order=1,
+                mode=SALE_EULERIAN, c_hg=0.1) -> sale_config:
     return sale_config(nx, ny, nz, (C.c_double * 3)(*lo), (C.c_double * 3)(*hi), gamma, cfl, c_quad,
-                       c_lin, t_end, precision, (C.c_int32 * 6)(*([SALE_BC_REFLECT] * 6)), remap_order)
+                       c_lin, t_end, precision, (C.c_int32 * 6)(*([SALE_BC_REFLECT] * 6)), remap_order,
+                       mode, c_hg)
 
 
 def sod_problem(x_split=0.5, rhoL=1.0, pL=1.0, rhoR=0.125, pR=0.1, t0=0.0, step0=0) -> sale_problem:

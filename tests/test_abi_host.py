@@ -55,7 +55,8 @@ def test_struct_layout_matches_header(tmp_path):
 @pytest.mark.parametrize("bad", [
     dict(nx=0), dict(ny=-1), dict(nx=812, ny=812, nz=812), dict(gamma=1.0), dict(cfl=0.0), dict(cfl=1.0), dict(c_quad=-1.0),
     dict(t_end=-1.0), dict(precision=7), dict(hi=(0.0, 1.0, 1.0)), dict(remap_order=3),
-    dict(remap_order=-1),
+    dict(remap_order=-1), dict(mode=2), dict(c_hg=-0.1), dict(c_hg=float("nan")),
+    dict(mode=1, precision=1), dict(mode=1, remap_order=2),
 ])
 def test_invalid_config_rejected(bad):
     kw = dict(nx=4, ny=4, nz=4)

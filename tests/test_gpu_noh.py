@@ -1,8 +1,7 @@
 """GPU parity on the Noh implosion (SALE_NOH; Sec. I-D lists the problem among
 those ScalSALE solves, in 1D, 2D and 3D), through the C ABI.
 
-Bars: the initial state is the oracle's (cells bitwise, velocities to a
-few ulp); FP64 trajectories match the FP64 oracle to 1e-12 per field after
+Bars: the initial state is bitwise the oracle's; FP64 trajectories match the FP64 oracle to 1e-12 per field after
 every step compared (planar, cylindrical
 and spherical runs on ragged meshes, and whole runs to t = 0.6); at the
 benchmark's 128^3 size one step from a developed state matches the oracle
@@ -37,23 +36,14 @@ def oracle_noh(cfg, dims):
 
 
 @pytest.mark.parametrize("dims", [1, 2, 3])
-def test_noh_initial_state_matches_the_oracle(dims):
-    """Cells bitwise; velocities within a few units in the last place (the
-    device square root is not always correctly rounded, and the quotient
-    r/|r| inherits its error)."""
+def test_noh_initial_state_is_bitwise_the_oracle(dims):
     say("noh init", dims)
     cfg = noh_cfg((13, 11, 9))
     r = sale.SaleRun(cfg, sale.noh_problem(dims=dims))
     _, s = oracle_noh(cfg, dims)
     got = r.fields()
-    for k in ("rho", "e"):
+    for k in FIELDS:
         assert np.array_equal(got[k], getattr(s, k)), k
-    for k in ("u", "v", "w"):
-        a, b = got[k], getattr(s, k)
-        ulps = np.abs(a - b) / np.spacing(np.maximum(np.abs(b), 1e-300))
-        say(k, "max ulp difference", float(ulps.max()))
-        assert np.all((a == 0) == (b == 0)), k
-        assert ulps.max() <= 4.0, k
 
 
 @pytest.mark.parametrize("n,dims,steps", [((40, 36, 33), 3, 60), ((70, 45, 1), 2, 80), ((130, 2, 3), 1, 120)])
