@@ -71,6 +71,8 @@ def parse():
                          "target); skips the autotuner")
     ap.add_argument("--precision-report", type=int, default=0, metavar="N",
                     help="also run the N^3 Sedov to t = 1 in FP64 and MIXED32 and report per-field errors")
+    ap.add_argument("--section", default="", choices=("", "latency", "sedov128", "noh128", "lagrange128"),
+                    help="run only this extra block and print its JSON (for profiling it)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run one plain device copy of 2 GiB (reference for HBM counters)")
     return ap.parse_args()
@@ -383,6 +385,11 @@ def main():
         sys.exit(2)
     from paper_2209_01983_amd import sale
 
+    if a.section:
+        block = {"latency": lambda: sod_latency(50), "sedov128": lambda: sedov128(3), "noh128": lambda: noh128(3),
+                 "lagrange128": lagrange128}[a.section]
+        print(json.dumps({a.section: block()}), flush=True)
+        return
     if a.copy_calibration:
         copy_calibration()
     n = a.n
