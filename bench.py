@@ -26,7 +26,7 @@ Also reported (one JSON line, extra keys):
                128^3, FP64: per-step throughput over a 100-step window after
                10 warm-up steps, kernel split (forces+nodes, energy+geometry).
   batched      256 runs (seeded mix of Sod / Sedov, edges 16..64), MIXED32,
-               200 steps each in ONE persistent launch: aggregate
+               200 steps each in ONE pool advance (lockstep launches): aggregate
                cell-updates/s, makespan, per-run latency p50/p99; the same
                runs one after another on the plain FP64 path.
   serving      seeded Poisson trace (50 requests/s, cubic 32^3..192^3,
@@ -274,7 +274,7 @@ def batched(seq_fp64=True):
     r32 = workloads.run_batched(reqs, steps, sale.SALE_MIXED32)
     r32["pool"].close()
     out = {"workload": "256 runs, edges 16..64 (seed 2209), 128 sod + 128 sedov, 200 steps, "
-                       "one persistent launch",
+                       "one pool advance (lockstep launches over all runs)",
            "cells_total": sum(workloads.cells(r) for r in reqs),
            "mixed32": {"cell_updates_per_s": r32["cell_updates_per_s"], "makespan_s": r32["makespan_s"],
                        "latency_p50_s": pct(r32["latency_s"], 50), "latency_p99_s": pct(r32["latency_s"], 99)}}

@@ -221,12 +221,17 @@ void sale_destroy(sale_ctx *ctx);
 
 /* ---- pool: many independent runs, advanced together ------------------------
  * Batched and served runs: independent runs of different mesh sizes share one
- * caller-owned device arena and are advanced by one persistent kernel launch
- * per sale_pool_advance call. The launch pulls (round, phase, run, tile) work
- * items from a device queue; a run's phase waits only for that run's previous
- * phase (per-run counters), so runs of uneven size proceed independently. Each
- * run has its own time step. A run's results do not depend on which other runs
- * share the pool. */
+ * caller-owned device arena and are advanced together. By default an advance
+ * is a sequence of lockstep rounds: per round one launch computes every run's
+ * time step, one launch runs the Lagrange tiles of all runs and one the remap
+ * tiles of all runs (each run's z extent split in proportion to its share of
+ * the cells), so the kernel boundaries order the phases. With the environment
+ * variable SALE_POOL_PERSISTENT=1 at sale_pool_create, an advance is instead
+ * one persistent kernel launch that pulls (round, phase, run, tile) work items
+ * from a device queue, a run's phase waiting only for that run's previous
+ * phase. Each run has its own time step; a run that is done skips its tiles.
+ * A run's results do not depend on which other runs share the pool, nor on
+ * the advance mode. */
 typedef struct sale_pool sale_pool;
 
 /* Create a pool of up to max_runs slots over the device arena
@@ -243,8 +248,8 @@ int sale_pool_create(int32_t precision, int32_t max_runs, void *d_arena, size_t 
 int sale_pool_admit(sale_pool *pool, const sale_config *cfg, const sale_problem *prob, int64_t n_steps,
                     int32_t *slot);
 
-/* Enqueue one persistent launch advancing every unfinished admitted run by up
- * to max_steps_per_run steps (asynchronous). */
+/* Advance every unfinished admitted run by up to max_steps_per_run steps
+ * (asynchronous: lockstep rounds of launches, or one persistent launch). */
 int sale_pool_advance(sale_pool *pool, int32_t max_steps_per_run);
 
 /* Synchronise the stream and list, in done[0..*n_done), the slots whose run

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -518,6 +519,7 @@ struct sale_pool {
   std::vector<Ctl> h_ctl;
   sale::PoolQueue h_q;
   int resident;
+  bool lockstep;  // advance by lockstep launches (default) or by the persistent kernel
 };
 
 namespace sale_host {
@@ -615,6 +617,10 @@ int sale_pool_create(int32_t precision, int32_t max_runs, void *d_arena, size_t 
   p->free_list.push_back({hdr, arena_bytes - hdr});
   p->h_ctl.resize(max_runs);
   p->resident = precision == SALE_FP64 ? sale::pool_resident_blocks<double>() : sale::pool_resident_blocks<float>();
+  // SALE_POOL_PERSISTENT=1 selects the persistent-kernel advance (one launch
+  // per advance, device-side phase waits) instead of lockstep launches
+  const char *pers = getenv("SALE_POOL_PERSISTENT");
+  p->lockstep = !(pers && pers[0] == '1');
   *out = p;
   return SALE_OK;
 }
@@ -696,6 +702,45 @@ int sale_pool_advance(sale_pool *p, int32_t max_steps_per_run) {
   }
   const int nact = (int)p->h_act.size();
   if (nact == 0) return SALE_OK;
+  if (p->lockstep) {
+    // z split of each run sized to its share of the advance's cells, about
+    // kLockBlocks blocks per launch in all (one segment for runs too small)
+    constexpr double kLockBlocks = 3072.0;
+    double cells = 0.0;
+    for (int k : p->h_act) cells += (double)p->slots[k].m.ncell;
+    p->h_prefA.assign(1, 0);
+    p->h_prefB.assign(1, 0);
+    for (int k : p->h_act) {
+      PoolSlot &sl = p->slots[k];
+      const int quota = (int)std::max(1.0, kLockBlocks * (double)sl.m.ncell / cells);
+      const sale::Grid2 ga = sale::grid_lagrange(sl.m, quota, sale::kPoolRows);
+      const sale::Grid2 gb = sale::grid_remap(sl.m, quota, sale::kPoolRows);
+      hipError_t ce;
+      if (p->precision == SALE_FP64) {
+        sl.r64.ga = ga, sl.r64.gb = gb;
+        ce = hipMemcpyAsync((sale::PoolRun<double> *)p->d_runs + k, &sl.r64, sizeof(sl.r64), hipMemcpyHostToDevice,
+                            p->stream);
+      } else {
+        sl.r32.ga = ga, sl.r32.gb = gb;
+        ce = hipMemcpyAsync((sale::PoolRun<float> *)p->d_runs + k, &sl.r32, sizeof(sl.r32), hipMemcpyHostToDevice,
+                            p->stream);
+      }
+      if (ce != hipSuccess) return hip_fail(ce, "sale_pool_advance");
+      p->h_prefA.push_back(p->h_prefA.back() + ga.blocks());
+      p->h_prefB.push_back(p->h_prefB.back() + gb.blocks());
+    }
+    const int totA = p->h_prefA.back(), totB = p->h_prefB.back();
+    HIP_TRY(hipMemcpyAsync(p->d_act, p->h_act.data(), nact * sizeof(int), hipMemcpyHostToDevice, p->stream));
+    HIP_TRY(hipMemcpyAsync(p->d_prefA, p->h_prefA.data(), (nact + 1) * sizeof(int), hipMemcpyHostToDevice, p->stream));
+    HIP_TRY(hipMemcpyAsync(p->d_prefB, p->h_prefB.data(), (nact + 1) * sizeof(int), hipMemcpyHostToDevice, p->stream));
+    if (p->precision == SALE_FP64)
+      HIP_TRY(sale::launch_pool_lockstep<double>((const sale::PoolRun<double> *)p->d_runs, p->d_act, p->d_prefA,
+                                                 p->d_prefB, nact, totA, totB, max_steps_per_run, p->stream));
+    else
+      HIP_TRY(sale::launch_pool_lockstep<float>((const sale::PoolRun<float> *)p->d_runs, p->d_act, p->d_prefA,
+                                                p->d_prefB, nact, totA, totB, max_steps_per_run, p->stream));
+    return SALE_OK;
+  }
   p->h_q.head = 0;
   p->h_q.nact = nact;
   p->h_q.rounds = max_steps_per_run;

@@ -35,6 +35,9 @@ namespace sale {
 namespace {
 
 constexpr int CH = kPoolRows;
+// register cap of the lockstep tile kernels: that of the single-run kernels
+// of the same tile rows (4 waves per SIMD for 16 rows)
+constexpr int waves_of_lock() { return CH == 12 || CH == 24 ? 3 : 4; }
 constexpr int NT = 32 * CH;
 constexpr int LDS_DOUBLES =
     lagrange_lds_doubles<CH>() > remap_lds_doubles<CH>() ? lagrange_lds_doubles<CH>() : remap_lds_doubles<CH>();
@@ -173,7 +176,86 @@ __global__ __launch_bounds__(NT, SALE_WAVES_POOL) void k_pool(const PoolRun<R> *
   }
 }
 
+// ---- lockstep advance: one launch per phase over the tiles of every active run
+// A round is three launches: begin (dt and done of every run), the Lagrange
+// tiles of all runs, the remap tiles of all runs. Kernel boundaries order the
+// phases, so nothing waits on the device; a run that is done skips its tiles
+// (its state stays in its buffer). Each run's grids carry a z split sized to
+// its share of the advance's cells.
+template <typename R>
+__global__ void k_lock_begin(const PoolRun<R> *__restrict__ runs, const int *__restrict__ act, int nact,
+                             int first) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= nact) return;
+  const PoolRun<R> &p = runs[act[q]];
+  Ctl *c = p.ctl;
+  if (first) {
+    c->step_target = p.step_target;
+    if (c->clk_first == 0) c->clk_first = wall_clock64();
+  }
+  begin_step(p.m, c, p.step_target);
+}
+
+template <typename R>
+__global__ __launch_bounds__(NT, waves_of_lock()) void k_lock_lagrange(const PoolRun<R> *__restrict__ runs,
+                                                                      const int *__restrict__ act,
+                                                                      const int *__restrict__ prefA, int nact) {
+  __shared__ double lds[lagrange_lds_doubles<CH>()];
+  const int g = xcd_logical_block(blockIdx.x, gridDim.x);
+  const int q = find_run(prefA, nact, g);
+  const PoolRun<R> &p = runs[act[q]];
+  Ctl *ctl = p.ctl;
+  if (ctl->done) return;
+  const RunArgs<R> a = args_of(p);
+  if (lagrange_tile<R, CH>(a, g - prefA[q], ctl->dt, lds)) atomicOr(&ctl->status, SALE_FLAG_TANGLE);
+}
+
+template <typename R>
+__global__ __launch_bounds__(NT, waves_of_lock()) void k_lock_remap(const PoolRun<R> *__restrict__ runs,
+                                                                   const int *__restrict__ act,
+                                                                   const int *__restrict__ prefB, int nact) {
+  __shared__ double lds[remap_lds_doubles<CH>()];
+  const int g = xcd_logical_block(blockIdx.x, gridDim.x);
+  const int q = find_run(prefB, nact, g);
+  const PoolRun<R> &p = runs[act[q]];
+  Ctl *ctl = p.ctl;
+  if (ctl->done) return;
+  const RunArgs<R> a = args_of(p);
+  double amax;
+  bool bad;
+  remap_tile<R, CH>(a, g - prefB[q], lds, &amax, &bad);
+  block_max_to_ctl<NT>(ctl, amax, bad);
+}
+
+// device clock of each run's last completed step
+template <typename R>
+__global__ void k_lock_stamp(const PoolRun<R> *__restrict__ runs, const int *__restrict__ act, int nact) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= nact) return;
+  Ctl *c = runs[act[q]].ctl;
+  if (!c->done) c->clk_last = wall_clock64();
+}
+
 }  // namespace
+
+template <typename R>
+hipError_t launch_pool_lockstep(const PoolRun<R> *runs, const int *act, const int *prefA, const int *prefB,
+                                int nact, int totA, int totB, int rounds, hipStream_t s) {
+  const int nb = (nact + 255) / 256;
+  for (int r = 0; r < rounds; r++) {
+    hipLaunchKernelGGL(k_lock_begin<R>, dim3(nb), dim3(256), 0, s, runs, act, nact, r == 0 ? 1 : 0);
+    hipLaunchKernelGGL(k_lock_lagrange<R>, dim3(totA), dim3(NT), 0, s, runs, act, prefA, nact);
+    hipLaunchKernelGGL(k_lock_remap<R>, dim3(totB), dim3(NT), 0, s, runs, act, prefB, nact);
+    hipLaunchKernelGGL(k_lock_stamp<R>, dim3(nb), dim3(256), 0, s, runs, act, nact);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+template hipError_t launch_pool_lockstep<double>(const PoolRun<double> *, const int *, const int *, const int *,
+                                                 int, int, int, int, hipStream_t);
+template hipError_t launch_pool_lockstep<float>(const PoolRun<float> *, const int *, const int *, const int *, int,
+                                                int, int, int, hipStream_t);
 
 template <typename R>
 hipError_t launch_pool_advance(PoolRun<R> *runs, const int *act, const int *prefA, const int *prefB,

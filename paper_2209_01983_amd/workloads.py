@@ -43,9 +43,9 @@ def arena_bytes_for(reqs, precision, slack=1 << 20):
 
 
 def run_batched(reqs, steps, precision, pool=None):
-    """All requests admitted into one pool and advanced by ONE persistent
-    launch of `steps` steps. Returns a dict: makespan (s, HIP events around
-    the launch), aggregate cell-updates/s, per-run latency (s, from the
+    """All requests admitted into one pool and advanced by ONE pool advance
+    of `steps` steps (lockstep launches over all runs, or the persistent
+    kernel). Returns a dict: makespan (s, HIP events around the advance), aggregate cell-updates/s, per-run latency (s, from the
     launch's first wave to the run's last completed step, device clock), and
     the pool with its slots (for result checks)."""
     import torch
@@ -114,7 +114,7 @@ def serve(trace, precision, budget_bytes, max_runs=512, slice_steps=25, keep=Non
     Requests enter a FIFO queue at their arrival time; the head is admitted
     into the pool whenever a slot and an arena range of the HBM budget are
     free (admission refuses otherwise, and the head waits). Admitted runs
-    advance together, `slice_steps` steps per persistent launch; between
+    advance together, `slice_steps` steps per pool advance; between
     launches finished runs are polled, their fields copied to the host (the
     result a client receives), their memory released, and newly arrived
     requests admitted. Latency = arrival -> fields on the host.

@@ -1,5 +1,6 @@
-"""GPU tests of the pool: many independent runs advanced by the persistent
-multi-run kernel, through the C ABI.
+"""GPU tests of the pool: many independent runs advanced together, through
+the C ABI, in both advance modes (lockstep launches over all runs, and the
+persistent multi-run kernel).
 
 Bars: every pool run matches the FP64 oracle run of the same problem and step
 count to 1e-12 per field (the single-run bar); a run's results are bitwise
@@ -21,6 +22,13 @@ from parity import FIELDS, assert_parity, grid_of, oracle_state, say  # noqa: E4
 pytestmark = pytest.mark.gpu
 
 ARENA = 256 << 20
+
+
+@pytest.fixture(autouse=True, params=["lockstep", "persistent"])
+def advance_mode(request, monkeypatch):
+    """Every pool test runs with both advance modes (read at pool creation)."""
+    monkeypatch.setenv("SALE_POOL_PERSISTENT", "1" if request.param == "persistent" else "0")
+    return request.param
 
 
 def user_prob(st):
