@@ -45,7 +45,7 @@ __device__ void hex_volume(const double X[8][3], double S[8][3], double &V) {
 #pragma unroll
   for (int a = 0; a < 8; a++) S[a][0] = S[a][1] = S[a][2] = 0.0;
   V = 0.0;
-#pragma unroll
+#pragma unroll 1  // one Gauss point at a time: fewer live registers
   for (int q = 0; q < 8; q++) {
     const double r0 = (q & 1) ? hi : lo, r1 = (q & 2) ? hi : lo, r2 = (q & 4) ? hi : lo;
     // weights of the four edges along each axis at this point
@@ -267,21 +267,14 @@ __global__ __launch_bounds__(TPL) void k_lag_nodes(Mesh m, Ctl *ctl, State<doubl
   z1[n] = z0[n] + dt * (0.5 * (uo[2] + un[2]));
 }
 
-// the next step's signal a / h of one cell of a state (positions X, node
-// velocities U, energy e, mass mc); 0 and `bad` if the cell is not admissible
-__device__ double signal_over_h(const Mesh &m, const double X[8][3], const double U[8][3], double e, double mc,
-                                bool &tangled) {
-  double S[8][3], V;
-  hex_volume(X, S, V);
-  if (!(V > 0.0)) {
-    tangled = true;
-    return 0.0;
-  }
+// the signal a / h of one cell from its geometry (positions X, corner
+// vectors S, volume V > 0), node velocities U and energy e
+__device__ double signal_of(const Mesh &m, const double X[8][3], const double S[8][3], double V,
+                            const double U[8][3], double e) {
   const double h = length_scale(X, V);
   const double cs = sqrt(m.ggm1 * fmax(e, 0.0));
   const CellKin kin = kinematics(S, U, V);
   const double a = cs + kin.smax + 4.0 * m.cq * h * fmax(-kin.D, 0.0);
-  (void)mc;
   return a / h;
 }
 
@@ -320,7 +313,7 @@ __global__ __launch_bounds__(TPL) void k_lag_energy(Mesh m, Ctl *ctl, State<doub
     ijk_of(c, m.nx, m.ny, i, j, k);
     const double dt = ctl->dt, mc = mass[c];
     double work = 0.0;
-#pragma unroll
+#pragma unroll 1
     for (int a = 0; a < 8; a++) {
       const int64_t n = node_at(m, i + (a & 1), j + ((a >> 1) & 1), k + ((a >> 2) & 1));
       const double ub[3] = {0.5 * (cur.u[n] + nxt.u[n]), 0.5 * (cur.v[n] + nxt.v[n]), 0.5 * (cur.w[n] + nxt.w[n])};
@@ -328,17 +321,17 @@ __global__ __launch_bounds__(TPL) void k_lag_energy(Mesh m, Ctl *ctl, State<doub
       for (int d = 0; d < 3; d++) work += F[(3 * a + d) * m.ncell + c] * ub[d];
     }
     const double en = cur.e[c] - dt * work / mc;
-    double X[8][3], U[8][3];
+    double X[8][3], S[8][3], V;
     load_corners(m, x1, y1, z1, i, j, k, X);
-    load_corners(m, nxt.u, nxt.v, nxt.w, i, j, k, U);
-    double S[8][3], V;
     hex_volume(X, S, V);
     nxt.e[c] = en;
     nxt.rho[c] = mc / V;
     if (!(V > 0.0)) tangled = true;
     if (!isfinite(en) || !(en >= 0.0)) numeric = true;
     if (!tangled && !numeric) {
-      r = signal_over_h(m, X, U, en, mc, tangled);
+      double U[8][3];
+      load_corners(m, nxt.u, nxt.v, nxt.w, i, j, k, U);
+      r = signal_of(m, X, S, V, U, en);
       if (!isfinite(r)) numeric = true, r = 0.0;
     }
   }
@@ -367,10 +360,14 @@ __global__ __launch_bounds__(TPL) void k_lag_init_cells(Mesh m, Ctl *ctl, State<
     mass[c] = s.rho[c] * m.V0;
     int i, j, k;
     ijk_of(c, m.nx, m.ny, i, j, k);
-    double X[8][3], U[8][3];
+    double X[8][3], U[8][3], S[8][3], V;
     load_corners(m, x, y, z, i, j, k, X);
     load_corners(m, s.u, s.v, s.w, i, j, k, U);
-    r = signal_over_h(m, X, U, s.e[c], mass[c], tangled);
+    hex_volume(X, S, V);
+    if (V > 0.0)
+      r = signal_of(m, X, S, V, U, s.e[c]);
+    else
+      tangled = true;
   }
   flags_and_max<TPL>(ctl, r, tangled, false);
 }
