@@ -46,7 +46,10 @@ struct sale_ctx {
 // in the buffer it started from), and the steps a context runs eagerly before
 // it captures one (a short run would not earn the capture back).
 constexpr int kGraphSteps = 8;
-constexpr long long kGraphAfter = 128;
+#ifndef SALE_GRAPH_AFTER
+#define SALE_GRAPH_AFTER 128
+#endif
+constexpr long long kGraphAfter = SALE_GRAPH_AFTER;
 
 namespace sale_host {
 

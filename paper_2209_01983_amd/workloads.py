@@ -107,13 +107,16 @@ Served = collections.namedtuple("Served", "index arrival admitted finished slot 
 
 
 def serve(trace, precision, budget_bytes, max_runs=512, slice_steps=25, keep=None, fetch=True,
-          clock=time.perf_counter, sleep=time.sleep):
+          clock=time.perf_counter, sleep=time.sleep, max_cells=None):
     """Continuous-batching server over a request trace (dicts with arrival
     time in s, kind, n, steps and the problem parameters).
 
     Requests enter a FIFO queue at their arrival time; the head is admitted
     into the pool whenever a slot and an arena range of the HBM budget are
-    free (admission refuses otherwise, and the head waits). Admitted runs
+    free (admission refuses otherwise, and the head waits) and, with
+    `max_cells`, while the admitted runs hold fewer cells than that (a cap on
+    how many runs share the GPU at once: fewer runs in flight finish sooner
+    each, as long as they still fill the chip). Admitted runs
     advance together, `slice_steps` steps per pool advance; between
     launches finished runs are polled, their fields copied to the host (the
     result a client receives), their memory released, and newly arrived
@@ -127,6 +130,7 @@ def serve(trace, precision, budget_bytes, max_runs=512, slice_steps=25, keep=Non
     pending = collections.deque(enumerate(trace))
     queue = collections.deque()
     active = {}          # slot -> (index, arrival, admitted)
+    active_cells = 0
     out = []
     busy_cells = 0       # cell-updates executed
     t_start = clock()
@@ -137,6 +141,8 @@ def serve(trace, precision, budget_bytes, max_runs=512, slice_steps=25, keep=Non
             queue.append(pending.popleft())
         while queue:
             i, req = queue[0]
+            if max_cells is not None and active and active_cells + cells(req) > max_cells:
+                break
             cfg, prob = request_problem(req, precision)
             slot = pool.admit(cfg, prob, req["steps"])
             if slot is None:
@@ -145,6 +151,7 @@ def serve(trace, precision, budget_bytes, max_runs=512, slice_steps=25, keep=Non
                 break
             queue.popleft()
             active[slot] = (i, req["arrival"], clock() - t_start)
+            active_cells += cells(req)
         if not active:
             if pending:
                 wait = pending[0][1]["arrival"] - (clock() - t_start)
@@ -156,6 +163,7 @@ def serve(trace, precision, budget_bytes, max_runs=512, slice_steps=25, keep=Non
         for slot in pool.poll():
             i, arr, adm = active.pop(slot)
             req = trace[i]
+            active_cells -= cells(req)
             fields = pool.fields(slot) if fetch or (keep and i in keep) else None
             t, n, _, flags = pool.state(slot)
             fin = clock() - t_start
@@ -173,5 +181,6 @@ def serve(trace, precision, budget_bytes, max_runs=512, slice_steps=25, keep=Non
     stats = {"requests": len(out), "wall_s": wall, "cell_updates_per_s": busy_cells / wall,
              "latency_p50_s": float(np.percentile(lat, 50)), "latency_p99_s": float(np.percentile(lat, 99)),
              "queue_p50_s": float(np.percentile(qd, 50)), "queue_p99_s": float(np.percentile(qd, 99)),
-             "launches": launches, "slice_steps": slice_steps, "budget_bytes": budget_bytes}
+             "launches": launches, "slice_steps": slice_steps, "budget_bytes": budget_bytes,
+             "max_cells": max_cells}
     return sorted(out, key=lambda s: s.index), stats
