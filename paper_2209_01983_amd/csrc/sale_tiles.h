@@ -367,8 +367,11 @@ __device__ bool lagrange_tile(const RunArgs<R> &a, int b, double dtd, double *ld
 // nodes. Iteration c:
 //   P1  Lagrangian results of cell plane c+1 (halo 2 below, 1 above) and u'
 //       of node plane c+1 into LDS (loaded one iteration earlier)
-//   P2  donor-cell fluxes of its x/y faces and of the z face at node plane c+1
-//   P3  M, rho^{n+1}, e^pre of cell plane c; net x/y fluxes of plane c+1
+//   P2  donor-cell fluxes of the cell's lower and upper x/y faces (a face's
+//       flux is formed by both of its cells, from the same operands, so
+//       both get the same bits and no barrier is needed to share it) and of
+//       the z face at node plane c+1; net x/y fluxes of plane c+1; M,
+//       rho^{n+1}, e^pre of cell plane c
 //   P4  dual fluxes (1/8 of the adjacent cells' face fluxes) and nodal masses
 //       of node plane c
 //   P5  momentum / kinetic-energy remap of node plane c: u^{n+1}, KE defect
@@ -396,10 +399,9 @@ __device__ void remap_tile(const RunArgs<R> &a, int b, double *lds, double *amax
   // half of a double slot when R is float
   enum {
     RL = 0, EL = 1, VX = 2, VY = 3,          // Lagrangian results of plane c+1    (P1-P2)
-    MX = 4, EX = 5, MY = 6, EY = 7,          // face fluxes of plane c+1           (P2-P3)
-    SX = 0, SY = 1, MM = 2, MO = 3, SZ = 8,  // flux and mass sums                (P3-P4)
-    PHX = 4, PHY = 5,                        // dual fluxes of node plane c        (P4-P5)
-    UN = 0, SP = 3, DK = 6,                  // 0..2 u^{n+1}; |u^{n+1}|; KE defect (P5-P6)
+    SX = 4, SY = 5, MM = 6, MO = 7, SZ = 8,  // flux and mass sums                (P2-P4)
+    PHX = 0, PHY = 1,                        // dual fluxes of node plane c        (P4-P5)
+    UN = 2, SP = 5, DK = 6,                  // 2..4 u^{n+1}; |u^{n+1}|; KE defect (P5-P6)
     NSLOT = 9
   };
   auto RS = [&](int s) { return reinterpret_cast<R(*)[CW]>(lds + s * CH * CW); };
@@ -476,42 +478,47 @@ __device__ void remap_tile(const RunArgs<R> &a, int b, double *lds, double *amax
     const R uB = UPR[rB][0][cj][ci], vB = UPR[rB][1][cj][ci], wB = UPR[rB][2][cj][ci];
     const R uC = UPR[rC][0][cj][ci], vC = UPR[rC][1][cj][ci], wC = UPR[rC][2][cj][ci];
     // ---- P2 --------------------------------------------------------------------------
-    R muz_n = 0, epz_n = 0;
+    R ep_c = 0;
     {
       const bool pl = c1 >= 0 && c1 < m.nz;
-      R mx = 0, ex = 0, my = 0, ey = 0;
-      if (pl && ci >= 1 && gi >= 1 && gi <= m.nx - 1 && gj >= 0 && gj < m.ny) {
-        const R dv = R(sVX[cj][ci]);
-        const int dn = sVX[cj][ci] > 0.0 ? ci - 1 : ci;
-        mx = RS(RL)[cj][dn] * dv;
-        ex = mx * RS(EL)[cj][dn];
-      }
-      if (pl && cj >= 1 && gj >= 1 && gj <= m.ny - 1 && gi >= 0 && gi < m.nx) {
-        const R dv = R(sVY[cj][ci]);
-        const int dn = sVY[cj][ci] > 0.0 ? cj - 1 : cj;
-        my = RS(RL)[dn][ci] * dv;
-        ey = my * RS(EL)[dn][ci];
-      }
+      // donor-cell fluxes through the x face at column x (between cells x-1
+      // and x) and the y face at row y of plane c+1; zero on walls and
+      // outside the mesh
+      auto xflux = [&](int x, int gx, R &mu, R &ep) {
+        mu = ep = R(0);
+        if (pl && x >= 1 && gx >= 1 && gx <= m.nx - 1 && gj >= 0 && gj < m.ny) {
+          const R dv = R(sVX[cj][x]);
+          const int dn = sVX[cj][x] > 0.0 ? x - 1 : x;
+          mu = RS(RL)[cj][dn] * dv;
+          ep = mu * RS(EL)[cj][dn];
+        }
+      };
+      auto yflux = [&](int y, int gy, R &mu, R &ep) {
+        mu = ep = R(0);
+        if (pl && y >= 1 && gy >= 1 && gy <= m.ny - 1 && gi >= 0 && gi < m.nx) {
+          const R dv = R(sVY[y][ci]);
+          const int dn = sVY[y][ci] > 0.0 ? y - 1 : y;
+          mu = RS(RL)[dn][ci] * dv;
+          ep = mu * RS(EL)[dn][ci];
+        }
+      };
+      R muz_n = 0, epz_n = 0;
       if (ccol && c1 >= 1 && c1 <= m.nz - 1) {  // z face between cells c and c+1
         const bool lower = dvz_n > 0.0;
         muz_n = (lower ? rl_c : rl_n) * R(dvz_n);
         epz_n = muz_n * (lower ? el_c : el_n);
       }
-      RS(MX)[cj][ci] = mx;
-      RS(EX)[cj][ci] = ex;
-      RS(MY)[cj][ci] = my;
-      RS(EY)[cj][ci] = ey;
-    }
-    __syncthreads();
-    // ---- P3 --------------------------------------------------------------------------
-    R ep_c = 0;
-    {
       R nm = 0, ne = 0, sx = 0, sy = 0, M = 0, mo = 0, sz = 0;
       if (r1 && ccol && c1 >= 0 && c1 < m.nz) {
-        nm = (RS(MX)[cj][ci + 1] - RS(MX)[cj][ci]) + (RS(MY)[cj + 1][ci] - RS(MY)[cj][ci]);
-        ne = (RS(EX)[cj][ci + 1] - RS(EX)[cj][ci]) + (RS(EY)[cj + 1][ci] - RS(EY)[cj][ci]);
-        sx = RS(MX)[cj][ci] + RS(MX)[cj][ci + 1];
-        sy = RS(MY)[cj][ci] + RS(MY)[cj + 1][ci];
+        R mxl, exl, mxu, exu, myl, eyl, myu, eyu;
+        xflux(ci, gi, mxl, exl);
+        xflux(ci + 1, gi + 1, mxu, exu);
+        yflux(cj, gj, myl, eyl);
+        yflux(cj + 1, gj + 1, myu, eyu);
+        nm = (mxu - mxl) + (myu - myl);
+        ne = (exu - exl) + (eyu - eyl);
+        sx = mxl + mxu;
+        sy = myl + myu;
       }
       if (r1 && ccol && c >= 0 && c < m.nz) {
         const R netm = nxm_c + (muz_n - muz_c);
@@ -528,20 +535,20 @@ __device__ void remap_tile(const RunArgs<R> &a, int b, double *lds, double *amax
         if (mine) plane_at<R>(a.nxt.rho, cpl, c, cix * (uint32_t)sizeof(R)) = rn;
         sz = muz_c + muz_n;
       }
-      RS(SX)[cj][ci] = sx;  // slots 0..3 (RL..VY) are dead since P2
+      RS(SX)[cj][ci] = sx;  // slots the phase does not read
       RS(SY)[cj][ci] = sy;
       RS(MM)[cj][ci] = M;
       RS(MO)[cj][ci] = mo;
       RS(SZ)[cj][ci] = sz;
       nxm_c = nm;
       nxe_c = ne;
+      // plane c+1 becomes plane c
+      rho_c = rho_n;
+      rl_c = rl_n;
+      el_c = el_n;
+      muz_c = muz_n;
+      epz_c = epz_n;
     }
-    // plane c+1 becomes plane c
-    rho_c = rho_n;
-    rl_c = rl_n;
-    el_c = el_n;
-    muz_c = muz_n;
-    epz_c = epz_n;
     __syncthreads();
     // ---- P4 --------------------------------------------------------------------------
     R phz = 0, mp = 0, mn = 0;
@@ -561,7 +568,7 @@ __device__ void remap_tile(const RunArgs<R> &a, int b, double *lds, double *amax
         mn = R(0.125) * (pm_c1 + pm);
         mp = R(0.125) * (pr_c1 + pr);
       }
-      RS(PHX)[cj][ci] = phx_c;  // dual fluxes of node plane c (slots dead since P3)
+      RS(PHX)[cj][ci] = phx_c;  // dual fluxes of node plane c (slots dead since P2)
       RS(PHY)[cj][ci] = phy_c;
       phx_c = R(0.125) * (qx_c + qx);  // node plane c+1
       phy_c = R(0.125) * (qy_c + qy);
