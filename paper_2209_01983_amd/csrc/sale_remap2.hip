@@ -253,17 +253,29 @@ __global__ __launch_bounds__(TPB2) void k_fix2(Mesh m, Ctl *ctl, State<R> cur, S
     } else {
       int i, j, k;
       cell_of(m, c, i, j, k);
+      // the cell's 8 nodes, loaded once: KE defects, speeds, divergence
+      R uu[2][2][2], vv[2][2][2], ww[2][2][2];
       R s = R(0), smax = R(0);
       for (int cc = 0; cc < 2; cc++)
         for (int b = 0; b < 2; b++)
           for (int aa = 0; aa < 2; aa++) {
             const int64_t nn = nidx(m, i + aa, j + b, k + cc);
             s += t.dk[nn];
-            smax = fmax(smax, speed(nxt.u[nn], nxt.v[nn], nxt.w[nn]));
+            uu[cc][b][aa] = nxt.u[nn];
+            vv[cc][b][aa] = nxt.v[nn];
+            ww[cc][b][aa] = nxt.w[nn];
+            smax = fmax(smax, speed(uu[cc][b][aa], vv[cc][b][aa], ww[cc][b][aa]));
           }
       const R en = t.epre[c] + R(0.125) * s;
       nxt.e[c] = en;
-      const R D = state_divergence(m, nxt, i, j, k);
+      // D as state_divergence forms it (same halves, same order)
+      R xh[2], yh[2], zh[2];
+      for (int cc = 0; cc < 2; cc++) {
+        xh[cc] = (uu[cc][0][1] - uu[cc][0][0]) + (uu[cc][1][1] - uu[cc][1][0]);
+        yh[cc] = (vv[cc][1][0] - vv[cc][0][0]) + (vv[cc][1][1] - vv[cc][0][1]);
+        zh[cc] = ((ww[cc][0][0] + ww[cc][0][1]) + ww[cc][1][0]) + ww[cc][1][1];
+      }
+      const R D = divergence(m, xh[0], xh[1], yh[0], yh[1], zh[0], zh[1]);
       const R sa = signal_from(m, D, en, smax);
       if (!(en >= R(0)) || !isfinite(en) || !isfinite(sa))
         bad = true;
