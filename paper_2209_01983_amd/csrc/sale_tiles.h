@@ -149,7 +149,10 @@ constexpr int remap_lds_doubles() {
 //       node's 8 cells as a per-plane sum carried one plane            (LDS)
 //   P4  swept volumes of the faces of cell plane k-1 (they need delta on node
 //       planes k-1 and k only) and its compatible-energy work
-//   P5  V^L, rho^L, e^L of cell plane k-1; hand-off to remap_tile
+//   P5  V^L, rho^L, e^L of cell plane k-1; hand-off to remap_tile. It needs
+//       the neighbours' x/y swept volumes, so it runs after the next
+//       iteration's P1 barrier (they stay in LDS until that iteration's P4):
+//       three barriers per plane instead of four.
 // Returns true if a tangled cell was seen.
 template <typename R, int CH>
 __device__ bool lagrange_tile(const RunArgs<R> &a, int b, double dtd, double *lds) {
@@ -212,6 +215,28 @@ __device__ bool lagrange_tile(const RunArgs<R> &a, int b, double dtd, double *ld
   fetch(Z0 - 2);
   settle(fu), settle(fv), settle(fw), settle(frho), settle(fe);
 
+  // ---- P5: V^L, rho^L, e^L of cell plane cp, from the x/y swept volumes P4
+  // left in LDS, the cell's z-face swept volumes (lower: h_vz, upper: still
+  // in dvz_lo) and its e^L and mass held in registers
+  double h_el = 0.0, h_vz = 0.0;
+  R h_m = 0;
+  auto finish = [&](int cp) {
+    if (own_cell && cp >= Z0 && cp < Z1) {
+      const double VL = m.V0 + (((sVX[cj][ci + 1] - sVX[cj][ci]) + (sVY[cj + 1][ci] - sVY[cj][ci])) + (dvz_lo - h_vz));
+      double rl = 0.0;
+      if (!(VL > 0.0))
+        tangle = true;
+      else
+        rl = (double)h_m / VL;
+      const uint32_t oR = cix * (uint32_t)sizeof(R);
+      plane_at<R>(a.geo.rl, cpl, cp, oR) = R(rl);
+      plane_at<R>(a.geo.el, cpl, cp, oR) = R(h_el);
+      plane_at<R>(a.geo.dvx, cpl, cp, oR) = R(sVX[cj][ci]);
+      plane_at<R>(a.geo.dvy, cpl, cp, oR) = R(sVY[cj][ci]);
+      plane_at<R>(a.geo.dvz, cpl, cp, oR) = R(h_vz);
+    }
+  };
+
   for (int k = Z0 - 2; k <= Z1; k++) {
     // ---- P1 ----
     const R un = fu, vn = fv, wn = fw, rho_k = frho, e_k = fe;
@@ -220,6 +245,8 @@ __device__ bool lagrange_tile(const RunArgs<R> &a, int b, double dtd, double *ld
     sU[1][cj][ci] = vn;
     sU[2][cj][ci] = wn;
     __syncthreads();
+    // ---- P5 of cell plane k-2 (its swept volumes are in LDS until P4) ----
+    finish(k - 2);
     // ---- P2 ----
     R ps = 0, mc = 0, imc = 0;
     {
@@ -333,29 +360,20 @@ __device__ bool lagrange_tile(const RunArgs<R> &a, int b, double dtd, double *ld
       sVX[cj][ci] = vx;
       sVY[cj][ci] = vy;
     }
-    __syncthreads();
-    settle(fu), settle(fv), settle(fw), settle(frho), settle(fe);  // loads issued in P1
-    // ---- P5: V^L, rho^L, e^L of cell plane k-1 ----
-    if (own_cell && plane_ok && cp >= Z0 && cp < Z1) {
-      const double VL =
-          m.V0 + (((sVX[cj][ci + 1] - sVX[cj][ci]) + (sVY[cj + 1][ci] - sVY[cj][ci])) + (dvz_up - dvz_lo));
-      double rl = 0.0;
-      if (!(VL > 0.0))
-        tangle = true;
-      else
-        rl = (double)m1 / VL;
-      const uint32_t oR = cix * (uint32_t)sizeof(R);
-      plane_at<R>(a.geo.rl, cpl, cp, oR) = R(rl);
-      plane_at<R>(a.geo.el, cpl, cp, oR) = R((double)e1 - (double)ps1 * work / (double)m1);
-      plane_at<R>(a.geo.dvx, cpl, cp, oR) = R(sVX[cj][ci]);
-      plane_at<R>(a.geo.dvy, cpl, cp, oR) = R(sVY[cj][ci]);
-      plane_at<R>(a.geo.dvz, cpl, cp, oR) = R(dvz_lo);
+    // P5 of this plane runs after the next plane's first barrier
+    if (own_cell && cp >= Z0 && cp < Z1) {
+      h_el = (double)e1 - (double)ps1 * work / (double)m1;
+      h_vz = dvz_lo;
+      h_m = m1;
     }
     dvz_lo = dvz_up;
     ps1 = ps;
     e1 = e_k;
     m1 = mc;
+    settle(fu), settle(fv), settle(fw), settle(frho), settle(fe);  // loads issued in P1
   }
+  __syncthreads();
+  finish(Z1 - 1);
   return tangle;
 }
 
@@ -396,12 +414,15 @@ __device__ void remap_tile(const RunArgs<R> &a, int b, double *lds, double *amax
                         (cj < 2 + TY || gj == m.ny);
 
   // LDS slots of 32 x CH values, reused across phases; R slots use the first
-  // half of a double slot when R is float
+  // half of a double slot when R is float. P1 of the next plane writes only
+  // slots 0..3 and the u' ring, which P6 does not read, so no barrier
+  // separates P6 from it; P2, which writes slots 4..8, comes after P1's
+  // barrier.
   enum {
     RL = 0, EL = 1, VX = 2, VY = 3,          // Lagrangian results of plane c+1    (P1-P2)
     SX = 4, SY = 5, MM = 6, MO = 7, SZ = 8,  // flux and mass sums                (P2-P4)
     PHX = 0, PHY = 1,                        // dual fluxes of node plane c        (P4-P5)
-    UN = 2, SP = 5, DK = 6,                  // 2..4 u^{n+1}; |u^{n+1}|; KE defect (P5-P6)
+    UN = 4, SP = 7, DK = 8,                  // 4..6 u^{n+1}; |u^{n+1}|; KE defect (P5-P6)
     NSLOT = 9
   };
   auto RS = [&](int s) { return reinterpret_cast<R(*)[CW]>(lds + s * CH * CW); };
@@ -689,8 +710,8 @@ __device__ void remap_tile(const RunArgs<R> &a, int b, double *lds, double *amax
       zn1 = zn;
       ep_c1 = ep_c;
     }
-    __syncthreads();
   }
+  __syncthreads();  // the last plane's P6 reads are done before the LDS is reused
   *amax_out = amax;
   *bad_out = bad;
 }
