@@ -38,9 +38,14 @@ constexpr int CH = kPoolRows;
 // register cap of the lockstep tile kernels: that of the single-run kernels
 // of the same tile rows (4 waves per SIMD for 16 rows)
 constexpr int waves_of_lock() { return CH == 12 || CH == 24 ? 3 : 4; }
+// the FP32 bulk remap tile of 16 rows fits 80 VGPRs and 40 KB of LDS: three
+// blocks per CU
+template <typename R>
+constexpr int waves_of_lock_remap() { return sizeof(R) == 4 && CH == 16 ? 6 : waves_of_lock(); }
 constexpr int NT = 32 * CH;
 constexpr int LDS_DOUBLES =
-    lagrange_lds_doubles<CH>() > remap_lds_doubles<CH>() ? lagrange_lds_doubles<CH>() : remap_lds_doubles<CH>();
+    lagrange_lds_doubles<CH>() > remap_lds_doubles<double, CH>() ? lagrange_lds_doubles<CH>()
+                                                                 : remap_lds_doubles<double, CH>();
 // Cap of one wait, in ticks of the 100 MHz constant clock. A wait normally
 // lasts at most one tile of the same run (milliseconds).
 constexpr long long kWaitTicks = 200000000ll;  // 2 s
@@ -211,10 +216,10 @@ __global__ __launch_bounds__(NT, waves_of_lock()) void k_lock_lagrange(const Poo
 }
 
 template <typename R>
-__global__ __launch_bounds__(NT, waves_of_lock()) void k_lock_remap(const PoolRun<R> *__restrict__ runs,
-                                                                   const int *__restrict__ act,
-                                                                   const int *__restrict__ prefB, int nact) {
-  __shared__ double lds[remap_lds_doubles<CH>()];
+__global__ __launch_bounds__(NT, waves_of_lock_remap<R>()) void k_lock_remap(const PoolRun<R> *__restrict__ runs,
+                                                                            const int *__restrict__ act,
+                                                                            const int *__restrict__ prefB, int nact) {
+  __shared__ double lds[remap_lds_doubles<R, CH>()];
   const int g = xcd_logical_block(blockIdx.x, gridDim.x);
   const int q = find_run(prefB, nact, g);
   const PoolRun<R> &p = runs[act[q]];

@@ -20,6 +20,12 @@ template <int CH>
 constexpr int waves_of() {
   return CH == 12 ? 3 : CH == 24 ? 3 : CH == 16 ? SALE_WAVES_16 : 4;
 }
+// The FP32 bulk remap tile of 16 rows fits 80 VGPRs and its LDS (bulk planes
+// as float) 40 KB: three blocks per CU.
+template <typename R, int CH>
+constexpr int remap_waves() {
+  return sizeof(R) == 4 && CH == 16 ? 6 : waves_of<CH>();
+}
 constexpr int TPB = 256;  // simple per-element kernels
 
 // ---------------------------------------------------------------------------------
@@ -38,8 +44,8 @@ __global__ __launch_bounds__(32 * CH, waves_of<CH>()) void k_lagrange(RunArgs<R>
 }
 
 template <typename R, int CH>
-__global__ __launch_bounds__(32 * CH, waves_of<CH>()) void k_remap(RunArgs<R> a) {
-  __shared__ double lds[remap_lds_doubles<CH>()];
+__global__ __launch_bounds__(32 * CH, (remap_waves<R, CH>())) void k_remap(RunArgs<R> a) {
+  __shared__ double lds[remap_lds_doubles<R, CH>()];
   const int b = xcd_logical_block(blockIdx.x, gridDim.x);
   if (a.ctl->done) {
     copy_tile<R, CH>(a, b);

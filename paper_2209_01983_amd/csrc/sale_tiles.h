@@ -130,9 +130,10 @@ template <int CH>
 constexpr int lagrange_lds_doubles() {
   return 13 * 32 * CH;
 }
-template <int CH>
+// (remap: two double planes, then 16 planes of the bulk type R)
+template <typename R, int CH>
 constexpr int remap_lds_doubles() {
-  return 18 * 32 * CH;
+  return (2 * 8 + 16 * (int)sizeof(R)) * 32 * CH / 8;
 }
 
 // ---------------------------------------------------------------------------------
@@ -413,22 +414,25 @@ __device__ void remap_tile(const RunArgs<R> &a, int b, double *lds, double *amax
   const bool own_node = ci >= 2 && cj >= 2 && gi <= m.nx && gj <= m.ny && (ci < 2 + TX || gi == m.nx) &&
                         (cj < 2 + TY || gj == m.ny);
 
-  // LDS slots of 32 x CH values, reused across phases; R slots use the first
-  // half of a double slot when R is float. P1 of the next plane writes only
-  // slots 0..3 and the u' ring, which P6 does not read, so no barrier
-  // separates P6 from it; P2, which writes slots 4..8, comes after P1's
-  // barrier.
+  // LDS: the x/y swept volumes of plane c+1 as double, then planes of R
+  // (32 x CH values each) reused across phases. P1 of the next plane writes
+  // only RL, EL, the swept volumes and the u' ring, which P6 does not read,
+  // so no barrier separates P6 from it; P2, which writes R planes 2..6, comes
+  // after P1's barrier.
   enum {
-    RL = 0, EL = 1, VX = 2, VY = 3,          // Lagrangian results of plane c+1    (P1-P2)
-    SX = 4, SY = 5, MM = 6, MO = 7, SZ = 8,  // flux and mass sums                (P2-P4)
+    RL = 0, EL = 1,                          // Lagrangian results of plane c+1    (P1-P2)
+    SX = 2, SY = 3, MM = 4, MO = 5, SZ = 6,  // flux and mass sums                (P2-P4)
     PHX = 0, PHY = 1,                        // dual fluxes of node plane c        (P4-P5)
-    UN = 4, SP = 7, DK = 8,                  // 4..6 u^{n+1}; |u^{n+1}|; KE defect (P5-P6)
-    NSLOT = 9
+    UN = 2, SP = 5, DK = 6,                  // 2..4 u^{n+1}; |u^{n+1}|; KE defect (P5-P6)
+    NSLOT = 7
   };
-  auto RS = [&](int s) { return reinterpret_cast<R(*)[CW]>(lds + s * CH * CW); };
-  double(*sVX)[CW] = reinterpret_cast<double(*)[CW]>(lds + VX * CH * CW);
-  double(*sVY)[CW] = reinterpret_cast<double(*)[CW]>(lds + VY * CH * CW);
-  R(*UPR)[3][CH][CW] = reinterpret_cast<R(*)[3][CH][CW]>(lds + NSLOT * CH * CW);  // [3][3]
+  double(*sVX)[CW] = reinterpret_cast<double(*)[CW]>(lds);
+  double(*sVY)[CW] = reinterpret_cast<double(*)[CW]>(lds + CH * CW);
+  R *const rbase = reinterpret_cast<R *>(lds + 2 * CH * CW);
+  auto RS = [&](int s) { return reinterpret_cast<R(*)[CW]>(rbase + s * CH * CW); };
+  R(*UPR)[3][CH][CW] = reinterpret_cast<R(*)[3][CH][CW]>(rbase + NSLOT * CH * CW);  // [3][3]
+  static_assert(2 * CH * CW * 8 + (NSLOT + 9) * CH * CW * (int)sizeof(R) <= remap_lds_doubles<R, CH>() * 8,
+                "remap LDS layout");
 
   const bool ccol = gi >= 0 && gi < m.nx && gj >= 0 && gj < m.ny;
   const bool ncol = gi >= 0 && gi <= m.nx && gj >= 0 && gj <= m.ny;
