@@ -29,17 +29,29 @@ constexpr int TPB2 = 256;
 
 inline int64_t blocks2(int64_t n) { return (n + TPB2 - 1) / TPB2; }
 
+// Harmonic mean of two one-sided differences of neighbouring means (zero
+// where they differ in sign): the limited change of the profile over one
+// cell. The slope is this over the spacing h; it is applied as the fraction
+// (h - |dv/A|) / (2h) of it (donor_weight), so a face needs one division per
+// field (the mean) instead of three.
 template <typename R>
-__device__ __forceinline__ R vanleer(R am, R ap) {
-  return (am * ap > R(0)) ? R(2) * am * ap / (am + ap) : R(0);
+__device__ __forceinline__ R vanleer(R dm, R dp) {
+  return (dm * dp > R(0)) ? R(2) * dm * dp / (dm + dp) : R(0);
 }
 
-// value of the donor's profile (mean q, slope) at the centroid of the swept
-// slab; dvA = swept volume / face area, > 0 when the donor is the lower cell
+// distance from the donor's centre to the swept slab's centroid, in units
+// of the cell: (h - |dvA|) / (2h); dvA = swept volume / face area
 template <typename R>
-__device__ __forceinline__ R donor_value(R q, R slope, R h, R dvA) {
-  const R off = R(0.5) * (h - fabs(dvA));
-  return dvA > R(0) ? q + slope * off : q - slope * off;
+__device__ __forceinline__ R donor_weight(R dvA, R ih) {
+  return R(0.5) - R(0.5) * (fabs(dvA) * ih);
+}
+
+// value of the donor's profile (mean q, limited change dq over one cell) at
+// the slab's centroid, on the face side of the donor: toward +axis when the
+// donor is the lower cell (lower = true)
+template <typename R>
+__device__ __forceinline__ R donor_value(R q, R dq, R wgt, bool lower) {
+  return lower ? q + dq * wgt : q - dq * wgt;
 }
 
 __device__ __forceinline__ void cell_of(const Mesh &m, int64_t c, int &i, int &j, int &k) {
@@ -65,8 +77,8 @@ __global__ __launch_bounds__(TPB2) void k_faces2(Mesh m, const Ctl *ctl, Geo<R> 
   const int n3[3] = {m.nx, m.ny, m.nz};
   const int64_t st[3] = {1, m.nx, (int64_t)m.nx * m.ny};
   const R *dvs[3] = {geo.dvx, geo.dvy, geo.dvz};
-  const R hs[3] = {R(m.dx), R(m.dy), R(m.dz)};
-  const R area[3] = {R(m.hyz), R(m.hzx), R(m.hxy)};
+  // 1 / (h A): the slab's thickness over the spacing is |dv| / (h A)
+  const R ihA[3] = {R(1) / (R(m.dx) * R(m.hyz)), R(1) / (R(m.dy) * R(m.hzx)), R(1) / (R(m.dz) * R(m.hxy))};
 #pragma unroll
   for (int a = 0; a < 3; a++) {
     R mu = R(0), eps = R(0);
@@ -75,16 +87,15 @@ __global__ __launch_bounds__(TPB2) void k_faces2(Mesh m, const Ctl *ctl, Geo<R> 
       const bool lower = dv > R(0);
       const int64_t dn = lower ? c - st[a] : c;
       const int di = lower ? idx[a] - 1 : idx[a];
-      R sr = R(0), se = R(0);
+      const R r0 = geo.rl[dn], e0 = geo.el[dn];
+      R rf = r0, ef = e0;
       if (di >= 1 && di + 1 < n3[a]) {
-        const R r0 = geo.rl[dn], rm = geo.rl[dn - st[a]], rp = geo.rl[dn + st[a]];
-        const R e0 = geo.el[dn], em = geo.el[dn - st[a]], ep = geo.el[dn + st[a]];
-        sr = vanleer((r0 - rm) / hs[a], (rp - r0) / hs[a]);
-        se = vanleer((e0 - em) / hs[a], (ep - e0) / hs[a]);
+        const R rm = geo.rl[dn - st[a]], rp = geo.rl[dn + st[a]];
+        const R em = geo.el[dn - st[a]], ep = geo.el[dn + st[a]];
+        const R wgt = donor_weight(dv, ihA[a]);
+        rf = donor_value(r0, vanleer(r0 - rm, rp - r0), wgt, lower);
+        ef = donor_value(e0, vanleer(e0 - em, ep - e0), wgt, lower);
       }
-      const R dvA = dv / area[a];
-      const R rf = donor_value(geo.rl[dn], sr, hs[a], dvA);
-      const R ef = donor_value(geo.el[dn], se, hs[a], dvA);
       mu = rf * dv;
       eps = mu * ef;
     }
@@ -147,8 +158,7 @@ __global__ __launch_bounds__(TPB2) void k_nodes2(Mesh m, Ctl *ctl, State<R> cur,
   const int64_t cst[3] = {1, m.nx, (int64_t)m.nx * m.ny};
   const int64_t nst[3] = {1, m.nx + 1, (int64_t)(m.nx + 1) * (m.ny + 1)};
   const R *dvs[3] = {geo.dvx, geo.dvy, geo.dvz};
-  const R hs[3] = {R(m.dx), R(m.dy), R(m.dz)};
-  const R area[3] = {R(m.hyz), R(m.hzx), R(m.hxy)};
+  const R ihA[3] = {R(1) / (R(m.dx) * R(m.hyz)), R(1) / (R(m.dy) * R(m.hzx)), R(1) / (R(m.dz) * R(m.hxy))};
   const R *vel[3] = {up, vp, wp};
   // nodal mass of the old state and of the new one
   R m_old = R(0), m_new = R(0);
@@ -164,26 +174,49 @@ __global__ __launch_bounds__(TPB2) void k_nodes2(Mesh m, Ctl *ctl, State<R> cur,
   const R u1 = up[n], v1 = vp[n], w1 = wp[n];
   R P[3] = {mp * u1, mp * v1, mp * w1};
   R K = R(0.5) * mp * (u1 * u1 + v1 * v1 + w1 * w1);
-  // mass flux and swept volume of the dual face of the edge from node
-  // (i,j,k) + (lo along axis a) to its +a neighbour: 1/8 of the lower plus
-  // upper face values of the (up to 4) cells sharing that edge
-  auto dual = [&](int a, int e0, R &phi, R &dv) {
-    R sp = R(0), sv = R(0);
+  // mass fluxes and swept volumes of the dual faces of the node's two edges
+  // along axis a (to the -a and to the +a neighbour): 1/8 of the lower plus
+  // upper face values of the (up to 4) cells sharing each edge. The cells of
+  // a transverse column at a-index i-1 and i share the face at node plane
+  // i, so each column reads three faces for both edges.
+  auto duals = [&](int a, R &phi_in, R &dv_in, R &phi_out, R &dv_out) {
     const int t1 = (a + 1) % 3, t2 = (a + 2) % 3;
+    const int ia = idx[a];
+    const bool has_in = ia >= 1, has_out = ia + 1 <= n3[a];
+    R spi = R(0), svi = R(0), spo = R(0), svo = R(0);
     for (int o2 = -1; o2 <= 0; o2++)
       for (int o1 = -1; o1 <= 0; o1++) {
         int ci[3] = {i, j, k};
-        ci[a] = e0;
         ci[t1] += o1;
         ci[t2] += o2;
-        if (!cell_in(m, ci[0], ci[1], ci[2])) continue;
-        const int64_t c = cidx(m, ci[0], ci[1], ci[2]);
-        const bool up_in = ci[a] + 1 < n3[a];
-        sp += t.mu[a][c] + (up_in ? t.mu[a][c + cst[a]] : R(0));
-        sv += dvs[a][c] + (up_in ? dvs[a][c + cst[a]] : R(0));
+        if (ci[t1] < 0 || ci[t1] >= n3[t1] || ci[t2] < 0 || ci[t2] >= n3[t2]) continue;
+        ci[a] = 0;
+        const int64_t c0 = cidx(m, ci[0], ci[1], ci[2]) + (int64_t)ia * cst[a];  // cell at a-index ia
+        // faces at node planes ia - 1, ia, ia + 1 (zero on the walls)
+        R mm = R(0), vm = R(0), m0 = R(0), v0 = R(0), mp = R(0), vp = R(0);
+        if (has_in) {
+          mm = t.mu[a][c0 - cst[a]];
+          vm = dvs[a][c0 - cst[a]];
+        }
+        if (has_out) {
+          m0 = t.mu[a][c0];
+          v0 = dvs[a][c0];
+          if (ia + 1 < n3[a]) {
+            mp = t.mu[a][c0 + cst[a]];
+            vp = dvs[a][c0 + cst[a]];
+          }
+          spo += m0 + mp;
+          svo += v0 + vp;
+        }
+        if (has_in) {
+          spi += mm + m0;
+          svi += vm + v0;
+        }
       }
-    phi = R(0.125) * sp;
-    dv = R(0.125) * sv;
+    phi_in = R(0.125) * spi;
+    dv_in = R(0.125) * svi;
+    phi_out = R(0.125) * spo;
+    dv_out = R(0.125) * svo;
   };
   // donor velocity of an edge: the donor node's limited linear profile along
   // the edge at the dual swept slab's centroid
@@ -191,14 +224,15 @@ __global__ __launch_bounds__(TPB2) void k_nodes2(Mesh m, Ctl *ctl, State<R> cur,
     const bool lower = phi > R(0);
     const int64_t dn = lower ? nlo : nlo + nst[a];
     const int di = lower ? ilo : ilo + 1;
-    const R dvA = lower ? fabs(dv / area[a]) : -fabs(dv / area[a]);
     const bool both = di >= 1 && di + 1 <= n3[a];
+    const R wgt = donor_weight(dv, ihA[a]);
+    // the slab lies on the +a side of the donor when the donor is the lower
+    // node and the dual swept volume is not zero
+    const bool plus = lower && dv != R(0);
 #pragma unroll
     for (int q = 0; q < 3; q++) {
       const R v0 = vel[q][dn];
-      R sl = R(0);
-      if (both) sl = vanleer((v0 - vel[q][dn - nst[a]]) / hs[a], (vel[q][dn + nst[a]] - v0) / hs[a]);
-      ud[q] = both ? donor_value(v0, sl, hs[a], dvA) : v0;
+      ud[q] = both ? donor_value(v0, vanleer(v0 - vel[q][dn - nst[a]], vel[q][dn + nst[a]] - v0), wgt, plus) : v0;
     }
   };
   auto flow = [&](R phi, const R ud[3], R sgn) {
@@ -208,17 +242,17 @@ __global__ __launch_bounds__(TPB2) void k_nodes2(Mesh m, Ctl *ctl, State<R> cur,
     K += sgn * (phi * R(0.5) * (ud[0] * ud[0] + ud[1] * ud[1] + ud[2] * ud[2]));
   };
   for (int a = 0; a < 3; a++) {
+    R phi_in, dv_in, phi_out, dv_out;
+    duals(a, phi_in, dv_in, phi_out, dv_out);
     if (idx[a] + 1 <= n3[a]) {  // edge to the +a neighbour: outflow
-      R phi, dv, ud[3];
-      dual(a, idx[a], phi, dv);
-      donor(a, n, idx[a], phi, dv, ud);
-      flow(phi, ud, R(-1));
+      R ud[3];
+      donor(a, n, idx[a], phi_out, dv_out, ud);
+      flow(phi_out, ud, R(-1));
     }
     if (idx[a] - 1 >= 0) {  // edge from the -a neighbour: inflow
-      R phi, dv, ud[3];
-      dual(a, idx[a] - 1, phi, dv);
-      donor(a, n - nst[a], idx[a] - 1, phi, dv, ud);
-      flow(phi, ud, R(1));
+      R ud[3];
+      donor(a, n - nst[a], idx[a] - 1, phi_in, dv_in, ud);
+      flow(phi_in, ud, R(1));
     }
   }
   R un = R(0), vn = R(0), wn = R(0), dk = R(0);
@@ -255,7 +289,7 @@ __global__ __launch_bounds__(TPB2) void k_fix2(Mesh m, Ctl *ctl, State<R> cur, S
       cell_of(m, c, i, j, k);
       // the cell's 8 nodes, loaded once: KE defects, speeds, divergence
       R uu[2][2][2], vv[2][2][2], ww[2][2][2];
-      R s = R(0), smax = R(0);
+      R s = R(0), s2max = R(0);  // the largest |u|^2: one square root per cell
       for (int cc = 0; cc < 2; cc++)
         for (int b = 0; b < 2; b++)
           for (int aa = 0; aa < 2; aa++) {
@@ -264,8 +298,11 @@ __global__ __launch_bounds__(TPB2) void k_fix2(Mesh m, Ctl *ctl, State<R> cur, S
             uu[cc][b][aa] = nxt.u[nn];
             vv[cc][b][aa] = nxt.v[nn];
             ww[cc][b][aa] = nxt.w[nn];
-            smax = fmax(smax, speed(uu[cc][b][aa], vv[cc][b][aa], ww[cc][b][aa]));
+            const R u0 = uu[cc][b][aa], v0 = vv[cc][b][aa], w0 = ww[cc][b][aa];
+            s2max = fmax(s2max, fma(w0, w0, fma(v0, v0, u0 * u0)));  // speed()'s argument
           }
+      // the square root is monotone, so this is the largest speed() of the 8 nodes
+      const R smax = sqrt(s2max);
       const R en = t.epre[c] + R(0.125) * s;
       nxt.e[c] = en;
       // D as state_divergence forms it (same halves, same order)
