@@ -13,12 +13,13 @@
 // masses, the dual fluxes, the kinetic-energy fix, walls, the next signal
 // speed -- is the first-order step's.
 //
-// Four passes, one thread per cell or node, neighbours read through the
-// caches (a direct form; the first-order remap is the tiled one):
+// Four passes; the first three one thread per cell or node with neighbours
+// read through the caches (a direct form; the first-order remap is tiled):
 //   k_faces2  fluxes through each cell's three lower faces
 //   k_cells2  M, rho^{n+1}, e^pre
 //   k_nodes2  dual fluxes, reconstructed donor velocities, u^{n+1}, KE defect
-//   k_fix2    KE fix, e^{n+1}, the next signal speed (block max -> ctl)
+//   k_fix2    KE fix, e^{n+1}, the next signal speed (block max -> ctl); a
+//             z-marching tile, each node plane read once
 // A step after t_end or after an error flag copies the state instead.
 #include "sale_tiles.h"
 
@@ -275,53 +276,86 @@ __global__ __launch_bounds__(TPB2) void k_nodes2(Mesh m, Ctl *ctl, State<R> cur,
 }
 
 // ---- pass 4: kinetic-energy fix, new energy, next signal speed ------------------------
+// A 32 x 16 tile of node columns marched along z over one segment: each
+// node plane's u^{n+1}, v, w and KE defect are read once into LDS, a cell
+// column forms its lower-plane half (partial defect sum, largest |u|^2,
+// divergence halves) and finishes the cell when the upper plane arrives.
+// Sums run in the order of the cell's 8 nodes (x fastest, then y, then z),
+// as in the gather form of the same pass.
+constexpr int FW = 32, FH = 16, FTX = FW - 1, FTY = FH - 1;
+
 template <typename R>
-__global__ __launch_bounds__(TPB2) void k_fix2(Mesh m, Ctl *ctl, State<R> cur, State<R> nxt, Rem2<R> t) {
-  const int64_t c = blockIdx.x * (int64_t)TPB2 + threadIdx.x;
-  const bool done = ctl->done;
+__global__ __launch_bounds__(FW * FH) void k_fix2(Mesh m, Ctl *ctl, State<R> cur, State<R> nxt, Rem2<R> t, Grid2 g) {
+  __shared__ R sU[FH][FW], sV[FH][FW], sW[FH][FW], sQ[FH][FW];
+  int tx, ty, seg;
+  tile_of(g, blockIdx.x, tx, ty, seg);
+  const int ci = threadIdx.x % FW, cj = threadIdx.x / FW;
+  const int gi = tx * FTX + ci, gj = ty * FTY + cj;  // node column; cell column when owned
+  const int Z0 = seg * g.seglen;
+  const int Z1 = seg == g.nseg - 1 ? m.nz : Z0 + g.seglen;  // cell planes [Z0, Z1)
+  const bool ncol = gi <= m.nx && gj <= m.ny;
+  const bool own = ci < FTX && cj < FTY && gi < m.nx && gj < m.ny;
+  const int64_t cpl = (int64_t)m.nx * m.ny, npl = (int64_t)(m.nx + 1) * (m.ny + 1);
+  const int64_t cix = own ? gi + (int64_t)m.nx * gj : 0, nix = ncol ? gi + (int64_t)(m.nx + 1) * gj : 0;
+  if (ctl->done) {  // uniform: the state is carried over
+    if (own)
+      for (int k = Z0; k < Z1; k++) nxt.e[cix + k * cpl] = cur.e[cix + k * cpl];
+    return;
+  }
+  R fu = 0, fv = 0, fw = 0, fq = 0;  // node plane loads, one plane ahead
+  auto fetch = [&](int k) {
+    fu = fv = fw = fq = R(0);
+    if (ncol && k <= m.nz) {
+      const int64_t q = nix + k * npl;
+      fu = nxt.u[q];
+      fv = nxt.v[q];
+      fw = nxt.w[q];
+      fq = t.dk[q];
+    }
+  };
+  fetch(Z0);
+  R s_lo = 0, s2_lo = 0, xh_lo = 0, yh_lo = 0, zh_lo = 0;  // lower node plane of the cell
   double a = 0.0;
   bool bad = false;
-  if (c < m.ncell) {
-    if (done) {
-      nxt.e[c] = cur.e[c];
-    } else {
-      int i, j, k;
-      cell_of(m, c, i, j, k);
-      // the cell's 8 nodes, loaded once: KE defects, speeds, divergence
-      R uu[2][2][2], vv[2][2][2], ww[2][2][2];
-      R s = R(0), s2max = R(0);  // the largest |u|^2: one square root per cell
-      for (int cc = 0; cc < 2; cc++)
-        for (int b = 0; b < 2; b++)
-          for (int aa = 0; aa < 2; aa++) {
-            const int64_t nn = nidx(m, i + aa, j + b, k + cc);
-            s += t.dk[nn];
-            uu[cc][b][aa] = nxt.u[nn];
-            vv[cc][b][aa] = nxt.v[nn];
-            ww[cc][b][aa] = nxt.w[nn];
-            const R u0 = uu[cc][b][aa], v0 = vv[cc][b][aa], w0 = ww[cc][b][aa];
-            s2max = fmax(s2max, fma(w0, w0, fma(v0, v0, u0 * u0)));  // speed()'s argument
-          }
-      // the square root is monotone, so this is the largest speed() of the 8 nodes
-      const R smax = sqrt(s2max);
-      const R en = t.epre[c] + R(0.125) * s;
-      nxt.e[c] = en;
-      // D as state_divergence forms it (same halves, same order)
-      R xh[2], yh[2], zh[2];
-      for (int cc = 0; cc < 2; cc++) {
-        xh[cc] = (uu[cc][0][1] - uu[cc][0][0]) + (uu[cc][1][1] - uu[cc][1][0]);
-        yh[cc] = (vv[cc][1][0] - vv[cc][0][0]) + (vv[cc][1][1] - vv[cc][0][1]);
-        zh[cc] = ((ww[cc][0][0] + ww[cc][0][1]) + ww[cc][1][0]) + ww[cc][1][1];
+  for (int k = Z0; k <= Z1; k++) {  // node plane k: upper plane of cell k-1, lower of cell k
+    sU[cj][ci] = fu;
+    sV[cj][ci] = fv;
+    sW[cj][ci] = fw;
+    sQ[cj][ci] = fq;
+    fetch(k + 1);
+    __syncthreads();
+    if (own) {
+      const R u00 = sU[cj][ci], u01 = sU[cj][ci + 1], u10 = sU[cj + 1][ci], u11 = sU[cj + 1][ci + 1];
+      const R v00 = sV[cj][ci], v01 = sV[cj][ci + 1], v10 = sV[cj + 1][ci], v11 = sV[cj + 1][ci + 1];
+      const R w00 = sW[cj][ci], w01 = sW[cj][ci + 1], w10 = sW[cj + 1][ci], w11 = sW[cj + 1][ci + 1];
+      const R q00 = sQ[cj][ci], q01 = sQ[cj][ci + 1], q10 = sQ[cj + 1][ci], q11 = sQ[cj + 1][ci + 1];
+      const R s2 = fmax(fmax(fma(w00, w00, fma(v00, v00, u00 * u00)), fma(w01, w01, fma(v01, v01, u01 * u01))),
+                        fmax(fma(w10, w10, fma(v10, v10, u10 * u10)), fma(w11, w11, fma(v11, v11, u11 * u11))));
+      const R xh = (u01 - u00) + (u11 - u10);
+      const R yh = (v10 - v00) + (v11 - v01);
+      const R zh = ((w00 + w01) + w10) + w11;
+      if (k > Z0) {  // finish cell k-1
+        const R s = (((s_lo + q00) + q01) + q10) + q11;
+        const int64_t c = cix + (k - 1) * cpl;
+        const R en = t.epre[c] + R(0.125) * s;
+        nxt.e[c] = en;
+        const R D = divergence(m, xh_lo, xh, yh_lo, yh, zh_lo, zh);
+        // the square root is monotone: this is the largest speed() of the 8 nodes
+        const R sa = signal_from(m, D, en, sqrt(fmax(s2_lo, s2)));
+        if (!(en >= R(0)) || !isfinite(en) || !isfinite(sa))
+          bad = true;
+        else
+          a = fmax(a, (double)sa);
       }
-      const R D = divergence(m, xh[0], xh[1], yh[0], yh[1], zh[0], zh[1]);
-      const R sa = signal_from(m, D, en, smax);
-      if (!(en >= R(0)) || !isfinite(en) || !isfinite(sa))
-        bad = true;
-      else
-        a = (double)sa;
+      s_lo = ((q00 + q01) + q10) + q11;
+      s2_lo = s2;
+      xh_lo = xh;
+      yh_lo = yh;
+      zh_lo = zh;
     }
+    __syncthreads();
   }
-  if (done) return;  // uniform: every thread of the launch sees the same flag
-  block_max_to_ctl<TPB2>(ctl, a, bad);
+  block_max_to_ctl<FW * FH>(ctl, a, bad);
 }
 
 }  // namespace
@@ -331,10 +365,19 @@ hipError_t launch_remap2(const Mesh &m, Ctl *ctl, const Work<R> &w, int cur, hip
   if (m.order != 2 || !w.r2.M) return hipErrorInvalidValue;
   const State<R> sc = w.s[cur], sn = w.s[1 - cur];
   const dim3 gc((unsigned)blocks2(m.ncell)), gn((unsigned)blocks2(m.nnode)), b(TPB2);
+  // KE-fix tiles: about 3072 blocks, at least 8 cell planes per segment
+  Grid2 gf;
+  gf.tx = (m.nx + FTX - 1) / FTX;
+  gf.ty = (m.ny + FTY - 1) / FTY;
+  const int maxseg = m.nz / 8 > 1 ? m.nz / 8 : 1;
+  int nseg = (3072 + gf.tx * gf.ty / 2) / (gf.tx * gf.ty);
+  nseg = nseg < 1 ? 1 : nseg > maxseg ? maxseg : nseg;
+  gf.seglen = (m.nz + nseg - 1) / nseg;
+  gf.nseg = (m.nz + gf.seglen - 1) / gf.seglen;
   hipLaunchKernelGGL(k_faces2<R>, gc, b, 0, s, m, ctl, w.geo, w.r2);
   hipLaunchKernelGGL(k_cells2<R>, gc, b, 0, s, m, ctl, sc, sn, w.geo, w.r2);
   hipLaunchKernelGGL(k_nodes2<R>, gn, b, 0, s, m, ctl, sc, sn, w.geo, w.up, w.vp, w.wp, w.r2);
-  hipLaunchKernelGGL(k_fix2<R>, gc, b, 0, s, m, ctl, sc, sn, w.r2);
+  hipLaunchKernelGGL(k_fix2<R>, dim3((unsigned)gf.blocks()), dim3(FW * FH), 0, s, m, ctl, sc, sn, w.r2, gf);
   return hipGetLastError();
 }
 
