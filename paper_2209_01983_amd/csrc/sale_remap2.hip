@@ -61,12 +61,6 @@ __device__ __forceinline__ void cell_of(const Mesh &m, int64_t c, int &i, int &j
   j = (int)(r % m.ny);
   k = (int)(r / m.ny);
 }
-__device__ __forceinline__ void node_of(const Mesh &m, int64_t n, int &i, int &j, int &k) {
-  i = (int)(n % (m.nx + 1));
-  const int64_t r = n / (m.nx + 1);
-  j = (int)(r % (m.ny + 1));
-  k = (int)(r / (m.ny + 1));
-}
 
 // ---- pass 1: face fluxes ---------------------------------------------------------
 template <typename R>
@@ -141,138 +135,231 @@ __global__ __launch_bounds__(TPB2) void k_cells2(Mesh m, Ctl *ctl, State<R> cur,
 }
 
 // ---- pass 3: node momentum and kinetic-energy remap ------------------------------------
+// A 32 x 16 tile of node columns (halo 2 on each side: the limited profiles
+// along x and y reach two nodes out) marched along z over one segment. For
+// node plane k the LDS holds u' of the plane and the face data of cell
+// planes k-1 and k (x/y mass fluxes and swept volumes, the z faces' lower +
+// upper sums, old and new cell masses; two buffers by plane parity); u' of
+// node planes k-2..k+2 (the z profiles) is carried in registers. Each input
+// value is read from memory once per tile.
+constexpr int NW = 32, NH = 16, NTX = NW - 4, NTY = NH - 4;
+
 template <typename R>
-__global__ __launch_bounds__(TPB2) void k_nodes2(Mesh m, Ctl *ctl, State<R> cur, State<R> nxt, Geo<R> geo,
-                                                 const R *up, const R *vp, const R *wp, Rem2<R> t) {
-  const int64_t n = blockIdx.x * (int64_t)TPB2 + threadIdx.x;
-  if (n >= m.nnode) return;
-  if (ctl->done) {
-    nxt.u[n] = cur.u[n];
-    nxt.v[n] = cur.v[n];
-    nxt.w[n] = cur.w[n];
+__global__ __launch_bounds__(NW * NH, 4) void k_nodes2(Mesh m, Ctl *ctl, State<R> cur, State<R> nxt, Geo<R> geo,
+                                                   const R *up, const R *vp, const R *wp, Rem2<R> t, Grid2 g) {
+  enum { MX, MY, VX, VY, SZ, VZ, MO, MN, NCP };
+  __shared__ R LU[3][NH][NW];         // u', v', w' of node plane k
+  __shared__ R LC[2][NCP][NH][NW];    // cell planes k-1, k (buffer = plane & 1)
+  int tx, ty, seg;
+  tile_of(g, blockIdx.x, tx, ty, seg);
+  const int ci = threadIdx.x % NW, cj = threadIdx.x / NW;
+  const int gi = tx * NTX + ci - 2, gj = ty * NTY + cj - 2;  // node column, and cell column (gi, gj)
+  const int Z0 = seg * g.seglen;
+  const int NZ1 = seg == g.nseg - 1 ? m.nz + 1 : Z0 + g.seglen;  // node planes [Z0, NZ1)
+  const bool ncol = gi >= 0 && gi <= m.nx && gj >= 0 && gj <= m.ny;
+  const bool ccol = gi >= 0 && gi < m.nx && gj >= 0 && gj < m.ny;
+  const bool own = ci >= 2 && cj >= 2 && ci < 2 + NTX && cj < 2 + NTY && gi <= m.nx && gj <= m.ny;
+  const int64_t cpl = (int64_t)m.nx * m.ny, npl = (int64_t)(m.nx + 1) * (m.ny + 1);
+  const int64_t cix = ccol ? gi + (int64_t)m.nx * gj : 0, nix = ncol ? gi + (int64_t)(m.nx + 1) * gj : 0;
+  if (ctl->done) {  // uniform: the state is carried over
+    if (own)
+      for (int k = Z0; k < NZ1; k++) {
+        const int64_t q = nix + k * npl;
+        nxt.u[q] = cur.u[q];
+        nxt.v[q] = cur.v[q];
+        nxt.w[q] = cur.w[q];
+      }
     return;
   }
-  int idx[3];
-  node_of(m, n, idx[0], idx[1], idx[2]);
-  const int i = idx[0], j = idx[1], k = idx[2];
-  const int n3[3] = {m.nx, m.ny, m.nz};
-  const int64_t cst[3] = {1, m.nx, (int64_t)m.nx * m.ny};
-  const int64_t nst[3] = {1, m.nx + 1, (int64_t)(m.nx + 1) * (m.ny + 1)};
-  const R *dvs[3] = {geo.dvx, geo.dvy, geo.dvz};
   const R ihA[3] = {R(1) / (R(m.dx) * R(m.hyz)), R(1) / (R(m.dy) * R(m.hzx)), R(1) / (R(m.dz) * R(m.hxy))};
-  const R *vel[3] = {up, vp, wp};
-  // nodal mass of the old state and of the new one
-  R m_old = R(0), m_new = R(0);
-  for (int cc = -1; cc <= 0; cc++)
-    for (int b = -1; b <= 0; b++)
-      for (int a = -1; a <= 0; a++)
-        if (cell_in(m, i + a, j + b, k + cc)) {
-          const int64_t c = cidx(m, i + a, j + b, k + cc);
-          m_old += cur.rho[c] * R(m.V0);
-          m_new += t.M[c];
-        }
-  const R mp = R(0.125) * m_old, mn = R(0.125) * m_new;
-  const R u1 = up[n], v1 = vp[n], w1 = wp[n];
-  R P[3] = {mp * u1, mp * v1, mp * w1};
-  R K = R(0.5) * mp * (u1 * u1 + v1 * v1 + w1 * w1);
-  // mass fluxes and swept volumes of the dual faces of the node's two edges
-  // along axis a (to the -a and to the +a neighbour): 1/8 of the lower plus
-  // upper face values of the (up to 4) cells sharing each edge. The cells of
-  // a transverse column at a-index i-1 and i share the face at node plane
-  // i, so each column reads three faces for both edges.
-  auto duals = [&](int a, R &phi_in, R &dv_in, R &phi_out, R &dv_out) {
-    const int t1 = (a + 1) % 3, t2 = (a + 2) % 3;
-    const int ia = idx[a];
-    const bool has_in = ia >= 1, has_out = ia + 1 <= n3[a];
-    R spi = R(0), svi = R(0), spo = R(0), svo = R(0);
-    for (int o2 = -1; o2 <= 0; o2++)
-      for (int o1 = -1; o1 <= 0; o1++) {
-        int ci[3] = {i, j, k};
-        ci[t1] += o1;
-        ci[t2] += o2;
-        if (ci[t1] < 0 || ci[t1] >= n3[t1] || ci[t2] < 0 || ci[t2] >= n3[t2]) continue;
-        ci[a] = 0;
-        const int64_t c0 = cidx(m, ci[0], ci[1], ci[2]) + (int64_t)ia * cst[a];  // cell at a-index ia
-        // faces at node planes ia - 1, ia, ia + 1 (zero on the walls)
-        R mm = R(0), vm = R(0), m0 = R(0), v0 = R(0), mp = R(0), vp = R(0);
-        if (has_in) {
-          mm = t.mu[a][c0 - cst[a]];
-          vm = dvs[a][c0 - cst[a]];
-        }
-        if (has_out) {
-          m0 = t.mu[a][c0];
-          v0 = dvs[a][c0];
-          if (ia + 1 < n3[a]) {
-            mp = t.mu[a][c0 + cst[a]];
-            vp = dvs[a][c0 + cst[a]];
+  const R V0 = R(m.V0);
+
+  // u' of the column at node planes k-2..k+2 (zero outside the mesh)
+  R zu[5], zv[5], zw[5];
+  auto node_load = [&](int p, R &u, R &v, R &w) {
+    u = v = w = R(0);
+    if (ncol && p >= 0 && p <= m.nz) {
+      const int64_t q = nix + p * npl;
+      u = up[q];
+      v = vp[q];
+      w = wp[q];
+    }
+  };
+  // face data of the column's cell at plane p (zero outside the mesh)
+  R f_mx, f_my, f_vx, f_vy, f_mo, f_mn;  // cell plane k+1
+  R z_m1, z_v1, z_m2, z_v2;              // z-face flux, swept volume of cell planes k+1, k+2
+  auto cell_load = [&](int p) {
+    f_mx = f_my = f_vx = f_vy = f_mo = f_mn = R(0);
+    if (ccol && p >= 0 && p < m.nz) {
+      const int64_t c = cix + p * cpl;
+      f_mx = t.mu[0][c];
+      f_my = t.mu[1][c];
+      f_vx = geo.dvx[c];
+      f_vy = geo.dvy[c];
+      f_mo = cur.rho[c] * V0;
+      f_mn = t.M[c];
+    }
+  };
+  auto zface_load = [&](int p, R &mz, R &vz) {
+    mz = vz = R(0);
+    if (ccol && p >= 0 && p < m.nz) {
+      const int64_t c = cix + p * cpl;
+      mz = t.mu[2][c];
+      vz = geo.dvz[c];
+    }
+  };
+  const int K0 = Z0 - 1;  // first pass: sums of cell plane Z0-1 for node plane Z0
+  for (int q = 0; q < 5; q++) node_load(K0 - 2 + q, zu[q], zv[q], zw[q]);
+  cell_load(K0);
+  R z_m0, z_v0;
+  zface_load(K0, z_m0, z_v0);
+  zface_load(K0 + 1, z_m1, z_v1);
+
+  for (int k = K0; k < NZ1; k++) {
+    R(*const C)[NH][NW] = LC[k & 1];        // cell plane k
+    R(*const Cm)[NH][NW] = LC[(k + 1) & 1];  // cell plane k-1 (written by the previous pass)
+    LU[0][cj][ci] = zu[2];
+    LU[1][cj][ci] = zv[2];
+    LU[2][cj][ci] = zw[2];
+    C[MX][cj][ci] = f_mx;
+    C[MY][cj][ci] = f_my;
+    C[VX][cj][ci] = f_vx;
+    C[VY][cj][ci] = f_vy;
+    C[SZ][cj][ci] = z_m0 + z_m1;  // lower + upper z face of the cell
+    C[VZ][cj][ci] = z_v0 + z_v1;
+    C[MO][cj][ci] = f_mo;
+    C[MN][cj][ci] = f_mn;
+    // next pass: cell plane k+1, z faces of k+2, node plane k+3
+    R nu, nv, nw;
+    cell_load(k + 1);
+    zface_load(k + 2, z_m2, z_v2);
+    node_load(k + 3, nu, nv, nw);
+    __syncthreads();
+    if (own && k >= Z0) {
+      // sums over the 4 cells of cell planes k-1 and k around the node (zero where absent)
+      auto c4 = [&](R(*P)[NH][NW], int s) {
+        return ((P[s][cj - 1][ci - 1] + P[s][cj - 1][ci]) + P[s][cj][ci - 1]) + P[s][cj][ci];
+      };
+      // x edges: cells (i, j-1..j) (outflow) and (i-1, j-1..j) (inflow), lower + upper face each
+      auto xo = [&](R(*P)[NH][NW], int s) {
+        return (P[s][cj - 1][ci] + P[s][cj - 1][ci + 1]) + (P[s][cj][ci] + P[s][cj][ci + 1]);
+      };
+      auto xi = [&](R(*P)[NH][NW], int s) {
+        return (P[s][cj - 1][ci - 1] + P[s][cj - 1][ci]) + (P[s][cj][ci - 1] + P[s][cj][ci]);
+      };
+      // y edges: cells (i-1..i, j) (outflow) and (i-1..i, j-1) (inflow)
+      auto yo = [&](R(*P)[NH][NW], int s) {
+        return (P[s][cj][ci - 1] + P[s][cj + 1][ci - 1]) + (P[s][cj][ci] + P[s][cj + 1][ci]);
+      };
+      auto yi = [&](R(*P)[NH][NW], int s) {
+        return (P[s][cj - 1][ci - 1] + P[s][cj][ci - 1]) + (P[s][cj - 1][ci] + P[s][cj][ci]);
+      };
+      {
+        const R mp = R(0.125) * (c4(Cm, MO) + c4(C, MO)), mn = R(0.125) * (c4(Cm, MN) + c4(C, MN));
+        const R u1 = zu[2], v1 = zv[2], w1 = zw[2];
+        R P0 = mp * u1, P1 = mp * v1, P2 = mp * w1;
+        R K = R(0.5) * mp * (u1 * u1 + v1 * v1 + w1 * w1);
+        auto flow = [&](R phi, R ud, R vd, R wd, R sgn) {
+          P0 += sgn * (phi * ud);
+          P1 += sgn * (phi * vd);
+          P2 += sgn * (phi * wd);
+          K += sgn * (phi * R(0.5) * (ud * ud + vd * vd + wd * wd));
+        };
+        // donor value of one component: limited linear profile of the donor
+        // (values qm, q0, qp at the donor and its two neighbours along the edge)
+        auto recon = [&](R qm, R q0, R qp, bool both, R wgt, bool plus) {
+          return both ? donor_value(q0, vanleer(q0 - qm, qp - q0), wgt, plus) : q0;
+        };
+        // in-plane edge along x (dx = 1, dy = 0) or y (dx = 0, dy = 1) from
+        // LDS column/row `lo` (the lower node) to lo + 1, global index glo
+        auto inplane = [&](int ax, int nlim, int glo, R phi, R dv, R sgn) {
+          const bool lower = phi > R(0);
+          const int dg = lower ? glo : glo + 1;
+          const bool both = dg >= 1 && dg + 1 <= nlim;
+          const R wgt = donor_weight(dv, ihA[ax]);
+          const bool plus = lower && dv != R(0);
+          const int dx = ax == 0, dy = ax == 1;
+          const int x0 = ci + (ax == 0 ? dg - gi : 0), y0 = cj + (ax == 1 ? dg - gj : 0);
+          const R ud = recon(LU[0][y0 - dy][x0 - dx], LU[0][y0][x0], LU[0][y0 + dy][x0 + dx], both, wgt, plus);
+          const R vd = recon(LU[1][y0 - dy][x0 - dx], LU[1][y0][x0], LU[1][y0 + dy][x0 + dx], both, wgt, plus);
+          const R wd = recon(LU[2][y0 - dy][x0 - dx], LU[2][y0][x0], LU[2][y0 + dy][x0 + dx], both, wgt, plus);
+          flow(phi, ud, vd, wd, sgn);
+        };
+        if (gi + 1 <= m.nx)
+          inplane(0, m.nx, gi, R(0.125) * (xo(Cm, MX) + xo(C, MX)), R(0.125) * (xo(Cm, VX) + xo(C, VX)), R(-1));
+        if (gi >= 1)
+          inplane(0, m.nx, gi - 1, R(0.125) * (xi(Cm, MX) + xi(C, MX)), R(0.125) * (xi(Cm, VX) + xi(C, VX)), R(1));
+        if (gj + 1 <= m.ny)
+          inplane(1, m.ny, gj, R(0.125) * (yo(Cm, MY) + yo(C, MY)), R(0.125) * (yo(Cm, VY) + yo(C, VY)), R(-1));
+        if (gj >= 1)
+          inplane(1, m.ny, gj - 1, R(0.125) * (yi(Cm, MY) + yi(C, MY)), R(0.125) * (yi(Cm, VY) + yi(C, VY)), R(1));
+        // z edges: the column's own u' at node planes k-2..k+2 (window slot 2 = plane k)
+        auto zedge = [&](int s, R phi, R dv, R sgn) {  // lower node in window slot s
+          const bool lower = phi > R(0);
+          const int d = lower ? s : s + 1;   // donor's window slot
+          const int dg = k - 2 + d;          // donor's node plane
+          const bool both = dg >= 1 && dg + 1 <= m.nz;
+          const R wgt = donor_weight(dv, ihA[2]);
+          const bool plus = lower && dv != R(0);
+          R ud, vd, wd;
+          if (lower && s == 2) {  // donor plane k
+            ud = recon(zu[1], zu[2], zu[3], both, wgt, plus);
+            vd = recon(zv[1], zv[2], zv[3], both, wgt, plus);
+            wd = recon(zw[1], zw[2], zw[3], both, wgt, plus);
+          } else if (d == 3) {  // donor plane k+1
+            ud = recon(zu[2], zu[3], zu[4], both, wgt, plus);
+            vd = recon(zv[2], zv[3], zv[4], both, wgt, plus);
+            wd = recon(zw[2], zw[3], zw[4], both, wgt, plus);
+          } else if (d == 1) {  // donor plane k-1
+            ud = recon(zu[0], zu[1], zu[2], both, wgt, plus);
+            vd = recon(zv[0], zv[1], zv[2], both, wgt, plus);
+            wd = recon(zw[0], zw[1], zw[2], both, wgt, plus);
+          } else {  // upper donor of the inflow edge: plane k
+            ud = recon(zu[1], zu[2], zu[3], both, wgt, plus);
+            vd = recon(zv[1], zv[2], zv[3], both, wgt, plus);
+            wd = recon(zw[1], zw[2], zw[3], both, wgt, plus);
           }
-          spo += m0 + mp;
-          svo += v0 + vp;
+          flow(phi, ud, vd, wd, sgn);
+        };
+        // z edges: the dual face between node planes k and k+1 is that of the
+        // 4 cells of plane k, the one between k-1 and k that of plane k-1
+        if (k + 1 <= m.nz) zedge(2, R(0.125) * c4(C, SZ), R(0.125) * c4(C, VZ), R(-1));
+        if (k >= 1) zedge(1, R(0.125) * c4(Cm, SZ), R(0.125) * c4(Cm, VZ), R(1));
+        R un = R(0), vn = R(0), wn = R(0), dk = R(0);
+        if (!(mn > R(0))) {
+          atomicOr(&ctl->status, SALE_FLAG_NUMERIC);
+        } else {
+          const R imn = R(1) / mn;
+          un = P0 * imn;
+          vn = P1 * imn;
+          wn = P2 * imn;
+          if (gi == 0 || gi == m.nx) un = R(0);
+          if (gj == 0 || gj == m.ny) vn = R(0);
+          if (k == 0 || k == m.nz) wn = R(0);
+          dk = (K - R(0.5) * mn * (un * un + vn * vn + wn * wn)) * imn;
         }
-        if (has_in) {
-          spi += mm + m0;
-          svi += vm + v0;
-        }
+        const int64_t q = nix + k * npl;
+        nxt.u[q] = un;
+        nxt.v[q] = vn;
+        nxt.w[q] = wn;
+        t.dk[q] = dk;
       }
-    phi_in = R(0.125) * spi;
-    dv_in = R(0.125) * svi;
-    phi_out = R(0.125) * spo;
-    dv_out = R(0.125) * svo;
-  };
-  // donor velocity of an edge: the donor node's limited linear profile along
-  // the edge at the dual swept slab's centroid
-  auto donor = [&](int a, int64_t nlo, int ilo, R phi, R dv, R ud[3]) {
-    const bool lower = phi > R(0);
-    const int64_t dn = lower ? nlo : nlo + nst[a];
-    const int di = lower ? ilo : ilo + 1;
-    const bool both = di >= 1 && di + 1 <= n3[a];
-    const R wgt = donor_weight(dv, ihA[a]);
-    // the slab lies on the +a side of the donor when the donor is the lower
-    // node and the dual swept volume is not zero
-    const bool plus = lower && dv != R(0);
+    }
+    __syncthreads();
 #pragma unroll
-    for (int q = 0; q < 3; q++) {
-      const R v0 = vel[q][dn];
-      ud[q] = both ? donor_value(v0, vanleer(v0 - vel[q][dn - nst[a]], vel[q][dn + nst[a]] - v0), wgt, plus) : v0;
+    for (int q = 0; q < 4; q++) {
+      zu[q] = zu[q + 1];
+      zv[q] = zv[q + 1];
+      zw[q] = zw[q + 1];
     }
-  };
-  auto flow = [&](R phi, const R ud[3], R sgn) {
-    P[0] += sgn * (phi * ud[0]);
-    P[1] += sgn * (phi * ud[1]);
-    P[2] += sgn * (phi * ud[2]);
-    K += sgn * (phi * R(0.5) * (ud[0] * ud[0] + ud[1] * ud[1] + ud[2] * ud[2]));
-  };
-  for (int a = 0; a < 3; a++) {
-    R phi_in, dv_in, phi_out, dv_out;
-    duals(a, phi_in, dv_in, phi_out, dv_out);
-    if (idx[a] + 1 <= n3[a]) {  // edge to the +a neighbour: outflow
-      R ud[3];
-      donor(a, n, idx[a], phi_out, dv_out, ud);
-      flow(phi_out, ud, R(-1));
-    }
-    if (idx[a] - 1 >= 0) {  // edge from the -a neighbour: inflow
-      R ud[3];
-      donor(a, n - nst[a], idx[a] - 1, phi_in, dv_in, ud);
-      flow(phi_in, ud, R(1));
-    }
+    zu[4] = nu;
+    zv[4] = nv;
+    zw[4] = nw;
+    z_m0 = z_m1;
+    z_v0 = z_v1;
+    z_m1 = z_m2;
+    z_v1 = z_v2;
   }
-  R un = R(0), vn = R(0), wn = R(0), dk = R(0);
-  if (!(mn > R(0))) {
-    atomicOr(&ctl->status, SALE_FLAG_NUMERIC);
-  } else {
-    const R imn = R(1) / mn;
-    un = P[0] * imn;
-    vn = P[1] * imn;
-    wn = P[2] * imn;
-    if (i == 0 || i == m.nx) un = R(0);
-    if (j == 0 || j == m.ny) vn = R(0);
-    if (k == 0 || k == m.nz) wn = R(0);
-    dk = (K - R(0.5) * mn * (un * un + vn * vn + wn * wn)) * imn;
-  }
-  nxt.u[n] = un;
-  nxt.v[n] = vn;
-  nxt.w[n] = wn;
-  t.dk[n] = dk;
 }
 
 // ---- pass 4: kinetic-energy fix, new energy, next signal speed ------------------------
@@ -364,19 +451,26 @@ template <typename R>
 hipError_t launch_remap2(const Mesh &m, Ctl *ctl, const Work<R> &w, int cur, hipStream_t s) {
   if (m.order != 2 || !w.r2.M) return hipErrorInvalidValue;
   const State<R> sc = w.s[cur], sn = w.s[1 - cur];
-  const dim3 gc((unsigned)blocks2(m.ncell)), gn((unsigned)blocks2(m.nnode)), b(TPB2);
-  // KE-fix tiles: about 3072 blocks, at least 8 cell planes per segment
-  Grid2 gf;
-  gf.tx = (m.nx + FTX - 1) / FTX;
-  gf.ty = (m.ny + FTY - 1) / FTY;
-  const int maxseg = m.nz / 8 > 1 ? m.nz / 8 : 1;
-  int nseg = (3072 + gf.tx * gf.ty / 2) / (gf.tx * gf.ty);
-  nseg = nseg < 1 ? 1 : nseg > maxseg ? maxseg : nseg;
-  gf.seglen = (m.nz + nseg - 1) / nseg;
-  gf.nseg = (m.nz + gf.seglen - 1) / gf.seglen;
+  const dim3 gc((unsigned)blocks2(m.ncell)), b(TPB2);
+  // tiles of the node and KE-fix passes: about 3072 blocks, at least 8
+  // planes per z segment
+  auto tiles = [](int cols, int rows, int planes, int tw, int th) {
+    Grid2 g;
+    g.tx = (cols + tw - 1) / tw;
+    g.ty = (rows + th - 1) / th;
+    const int maxseg = planes / 8 > 1 ? planes / 8 : 1;
+    int nseg = (3072 + g.tx * g.ty / 2) / (g.tx * g.ty);
+    nseg = nseg < 1 ? 1 : nseg > maxseg ? maxseg : nseg;
+    g.seglen = (planes + nseg - 1) / nseg;
+    g.nseg = (planes + g.seglen - 1) / g.seglen;
+    return g;
+  };
+  const Grid2 gnode = tiles(m.nx + 1, m.ny + 1, m.nz + 1, NTX, NTY);
+  const Grid2 gf = tiles(m.nx, m.ny, m.nz, FTX, FTY);
   hipLaunchKernelGGL(k_faces2<R>, gc, b, 0, s, m, ctl, w.geo, w.r2);
   hipLaunchKernelGGL(k_cells2<R>, gc, b, 0, s, m, ctl, sc, sn, w.geo, w.r2);
-  hipLaunchKernelGGL(k_nodes2<R>, gn, b, 0, s, m, ctl, sc, sn, w.geo, w.up, w.vp, w.wp, w.r2);
+  hipLaunchKernelGGL(k_nodes2<R>, dim3((unsigned)gnode.blocks()), dim3(NW * NH), 0, s, m, ctl, sc, sn, w.geo, w.up,
+                     w.vp, w.wp, w.r2, gnode);
   hipLaunchKernelGGL(k_fix2<R>, dim3((unsigned)gf.blocks()), dim3(FW * FH), 0, s, m, ctl, sc, sn, w.r2, gf);
   return hipGetLastError();
 }
