@@ -76,13 +76,12 @@ struct Geo {
 // Workspace of one run: two states (ping-pong), the Lagrangian end velocity
 // u' and the Lagrangian cell results, reduction partials, and one scratch
 // array of max(cells, nodes) doubles (conversions, derived fields).
-// Intermediates of the second-order remap (null for order 1): face mass and
-// internal-energy fluxes through each cell's three lower faces, the cells' new
-// masses and pre-fix energies, and the nodes' kinetic-energy defects per unit
-// new mass.
+// Intermediates of the second-order remap (null for order 1): mass fluxes
+// through each cell's three lower faces, the cells' new masses and pre-fix
+// energies, and the nodes' kinetic-energy defects per unit new mass.
 template <typename R>
 struct Rem2 {
-  R *mu[3], *eps[3];
+  R *mu[3];  // mass flux through each cell's lower face, per axis
   R *M, *epre;
   R *dk;
 };

@@ -13,22 +13,17 @@
 // masses, the dual fluxes, the kinetic-energy fix, walls, the next signal
 // speed -- is the first-order step's.
 //
-// Four passes; the first three one thread per cell or node with neighbours
-// read through the caches (a direct form; the first-order remap is tiled):
-//   k_faces2  fluxes through each cell's three lower faces
-//   k_cells2  M, rho^{n+1}, e^pre
+// Three passes, each a 32 x 16 tile of columns marched along z (every input
+// value read from memory once per tile, neighbours through LDS):
+//   k_cells2  fluxes through each cell's six faces, M, rho^{n+1}, e^pre
 //   k_nodes2  dual fluxes, reconstructed donor velocities, u^{n+1}, KE defect
-//   k_fix2    KE fix, e^{n+1}, the next signal speed (block max -> ctl); a
-//             z-marching tile, each node plane read once
+//   k_fix2    KE fix, e^{n+1}, the next signal speed (block max -> ctl)
 // A step after t_end or after an error flag copies the state instead.
 #include "sale_tiles.h"
 
 namespace sale {
 namespace {
 
-constexpr int TPB2 = 256;
-
-inline int64_t blocks2(int64_t n) { return (n + TPB2 - 1) / TPB2; }
 
 // Harmonic mean of two one-sided differences of neighbouring means (zero
 // where they differ in sign): the limited change of the profile over one
@@ -55,83 +50,157 @@ __device__ __forceinline__ R donor_value(R q, R dq, R wgt, bool lower) {
   return lower ? q + dq * wgt : q - dq * wgt;
 }
 
-__device__ __forceinline__ void cell_of(const Mesh &m, int64_t c, int &i, int &j, int &k) {
-  i = (int)(c % m.nx);
-  const int64_t r = c / m.nx;
-  j = (int)(r % m.ny);
-  k = (int)(r / m.ny);
-}
 
-// ---- pass 1: face fluxes ---------------------------------------------------------
-template <typename R>
-__global__ __launch_bounds__(TPB2) void k_faces2(Mesh m, const Ctl *ctl, Geo<R> geo, Rem2<R> t) {
-  const int64_t c = blockIdx.x * (int64_t)TPB2 + threadIdx.x;
-  if (c >= m.ncell || ctl->done) return;
-  int idx[3];
-  cell_of(m, c, idx[0], idx[1], idx[2]);
-  const int n3[3] = {m.nx, m.ny, m.nz};
-  const int64_t st[3] = {1, m.nx, (int64_t)m.nx * m.ny};
-  const R *dvs[3] = {geo.dvx, geo.dvy, geo.dvz};
-  // 1 / (h A): the slab's thickness over the spacing is |dv| / (h A)
-  const R ihA[3] = {R(1) / (R(m.dx) * R(m.hyz)), R(1) / (R(m.dy) * R(m.hzx)), R(1) / (R(m.dz) * R(m.hxy))};
-#pragma unroll
-  for (int a = 0; a < 3; a++) {
-    R mu = R(0), eps = R(0);
-    if (idx[a] > 0) {  // interior lower face between c - e_a and c
-      const R dv = dvs[a][c];
-      const bool lower = dv > R(0);
-      const int64_t dn = lower ? c - st[a] : c;
-      const int di = lower ? idx[a] - 1 : idx[a];
-      const R r0 = geo.rl[dn], e0 = geo.el[dn];
-      R rf = r0, ef = e0;
-      if (di >= 1 && di + 1 < n3[a]) {
-        const R rm = geo.rl[dn - st[a]], rp = geo.rl[dn + st[a]];
-        const R em = geo.el[dn - st[a]], ep = geo.el[dn + st[a]];
-        const R wgt = donor_weight(dv, ihA[a]);
-        rf = donor_value(r0, vanleer(r0 - rm, rp - r0), wgt, lower);
-        ef = donor_value(e0, vanleer(e0 - em, ep - e0), wgt, lower);
-      }
-      mu = rf * dv;
-      eps = mu * ef;
-    }
-    t.mu[a][c] = mu;
-    t.eps[a][c] = eps;
-  }
-}
+// ---- pass 1: face fluxes, cell masses, densities, pre-fix energies --------------------
+// A 32 x 16 tile of cell columns (halo 2 on each side: a face's donor
+// profile reaches one cell beyond the donor) marched along z over one
+// segment. Each cell forms the fluxes of its lower and upper faces on all
+// three axes; a face shared by two cells is formed by both from the same
+// operands, so both get the same bits. The LDS holds rho^L, e^L and the x/y
+// swept volumes of the cell plane; rho^L and e^L of cell planes k-2..k+2 (the
+// z profiles) are carried in registers. Stores the lower faces' mass fluxes
+// (for the node pass), M, rho^{n+1} and e^pre.
+constexpr int CW2 = 32, CH2 = 16, CTX = CW2 - 4, CTY = CH2 - 4;
 
-// ---- pass 2: cell masses, densities, pre-fix energies ---------------------------------
 template <typename R>
-__global__ __launch_bounds__(TPB2) void k_cells2(Mesh m, Ctl *ctl, State<R> cur, State<R> nxt, Geo<R> geo,
-                                                 Rem2<R> t) {
-  const int64_t c = blockIdx.x * (int64_t)TPB2 + threadIdx.x;
-  if (c >= m.ncell) return;
-  if (ctl->done) {
-    nxt.rho[c] = cur.rho[c];
+__global__ __launch_bounds__(CW2 * CH2) void k_cells2(Mesh m, Ctl *ctl, State<R> cur, State<R> nxt, Geo<R> geo,
+                                                     Rem2<R> t, Grid2 g) {
+  enum { RL, EL, DX, DY, NPL };
+  __shared__ R L[NPL][CH2][CW2];
+  int tx, ty, seg;
+  tile_of(g, blockIdx.x, tx, ty, seg);
+  const int ci = threadIdx.x % CW2, cj = threadIdx.x / CW2;
+  const int gi = tx * CTX + ci - 2, gj = ty * CTY + cj - 2;  // cell column
+  const int Z0 = seg * g.seglen;
+  const int Z1 = seg == g.nseg - 1 ? m.nz : Z0 + g.seglen;  // cell planes [Z0, Z1)
+  const bool ccol = gi >= 0 && gi < m.nx && gj >= 0 && gj < m.ny;
+  const bool own = ci >= 2 && cj >= 2 && ci < 2 + CTX && cj < 2 + CTY && ccol;
+  const int64_t cpl = (int64_t)m.nx * m.ny;
+  const int64_t cix = ccol ? gi + (int64_t)m.nx * gj : 0;
+  if (ctl->done) {  // uniform: the state is carried over
+    if (own)
+      for (int k = Z0; k < Z1; k++) nxt.rho[cix + k * cpl] = cur.rho[cix + k * cpl];
     return;
   }
-  int i, j, k;
-  cell_of(m, c, i, j, k);
-  const R zero = R(0);
-  // upper faces are the +axis neighbours' lower faces, or walls
-  const R mxu = i + 1 < m.nx ? t.mu[0][c + 1] : zero, exu = i + 1 < m.nx ? t.eps[0][c + 1] : zero;
-  const R myu = j + 1 < m.ny ? t.mu[1][c + m.nx] : zero, eyu = j + 1 < m.ny ? t.eps[1][c + m.nx] : zero;
-  const int64_t pz = (int64_t)m.nx * m.ny;
-  const R mzu = k + 1 < m.nz ? t.mu[2][c + pz] : zero, ezu = k + 1 < m.nz ? t.eps[2][c + pz] : zero;
-  const R netm = ((mxu - t.mu[0][c]) + (myu - t.mu[1][c])) + (mzu - t.mu[2][c]);
-  const R nete = ((exu - t.eps[0][c]) + (eyu - t.eps[1][c])) + (ezu - t.eps[2][c]);
-  const R rho = cur.rho[c];
-  const R M = rho * R(m.V0) - netm;
-  const R rn = rho - netm * R(m.iV0);
-  R ep = R(0);
-  if (!(M > R(0)) || !(rn > R(0)) || !isfinite(rn)) {
-    atomicOr(&ctl->status, SALE_FLAG_NUMERIC);
-  } else {
-    const R el = geo.el[c];
-    ep = el + (el * netm - nete) / M;
+  // 1 / (h A): the slab's thickness over the spacing is |dv| / (h A)
+  const R ihA[3] = {R(1) / (R(m.dx) * R(m.hyz)), R(1) / (R(m.dy) * R(m.hzx)), R(1) / (R(m.dz) * R(m.hxy))};
+
+  // rho^L, e^L of the column at cell planes k-2..k+2, z swept volumes of
+  // planes k, k+1 (the cell's lower and upper z faces); zero outside the mesh
+  R zr[5], ze[5], zv0, zv1;
+  auto lag_load = [&](int p, R &r, R &e) {
+    r = e = R(0);
+    if (ccol && p >= 0 && p < m.nz) {
+      r = geo.rl[cix + p * cpl];
+      e = geo.el[cix + p * cpl];
+    }
+  };
+  auto dvz_load = [&](int p) { return ccol && p >= 0 && p < m.nz ? geo.dvz[cix + p * cpl] : R(0); };
+  R f_dx = 0, f_dy = 0, f_rho = 0;  // x/y swept volumes and old density of the plane
+  auto plane_load = [&](int p) {
+    f_dx = f_dy = f_rho = R(0);
+    if (ccol && p >= 0 && p < m.nz) {
+      const int64_t c = cix + p * cpl;
+      f_dx = geo.dvx[c];
+      f_dy = geo.dvy[c];
+      f_rho = cur.rho[c];
+    }
+  };
+  for (int q = 0; q < 5; q++) lag_load(Z0 - 2 + q, zr[q], ze[q]);
+  zv0 = dvz_load(Z0);
+  zv1 = dvz_load(Z0 + 1);
+  plane_load(Z0);
+
+  // flux of mass and internal energy through a face: donor lower (dv > 0) or
+  // upper cell, its values (mean rm/r0/rp of the donor and its neighbours
+  // along the axis) taken from the limited linear profile when both
+  // neighbours exist (donor index di in [1, n-2])
+  auto flux = [&](R dv, int di, int n, R ih, R rm, R r0, R rp, R em, R e0, R ep, R &mu, R &eps) {
+    const bool lower = dv > R(0);
+    R rf = r0, ef = e0;
+    if (di >= 1 && di + 1 < n) {
+      const R wgt = donor_weight(dv, ih);
+      rf = donor_value(r0, vanleer(r0 - rm, rp - r0), wgt, lower);
+      ef = donor_value(e0, vanleer(e0 - em, ep - e0), wgt, lower);
+    }
+    mu = rf * dv;
+    eps = mu * ef;
+  };
+  // x or y face between LDS cells (x - dx, y - dy) and (x, y); gf is the
+  // global index of the upper cell along the axis (walls at 0 and n)
+  auto face_xy = [&](int ax, int x, int y, int gf, R &mu, R &eps) {
+    const int n = ax == 0 ? m.nx : m.ny;
+    mu = eps = R(0);
+    if (gf <= 0 || gf >= n) return;
+    const int dx = ax == 0, dy = ax == 1;
+    const R dv = L[ax == 0 ? DX : DY][y][x];
+    const bool lower = dv > R(0);
+    const int xd = lower ? x - dx : x, yd = lower ? y - dy : y;
+    flux(dv, lower ? gf - 1 : gf, n, ihA[ax], L[RL][yd - dy][xd - dx], L[RL][yd][xd], L[RL][yd + dy][xd + dx],
+         L[EL][yd - dy][xd - dx], L[EL][yd][xd], L[EL][yd + dy][xd + dx], mu, eps);
+  };
+
+  for (int k = Z0; k < Z1; k++) {
+    L[RL][cj][ci] = zr[2];
+    L[EL][cj][ci] = ze[2];
+    L[DX][cj][ci] = f_dx;
+    L[DY][cj][ci] = f_dy;
+    const R rho = f_rho;
+    // next pass: plane k+1, z swept volume of k+2, rho^L / e^L of k+3
+    R nr, ne;
+    plane_load(k + 1);
+    const R zv2 = dvz_load(k + 2);
+    lag_load(k + 3, nr, ne);
+    __syncthreads();
+    if (own) {
+      R mxl, exl, mxu, exu, myl, eyl, myu, eyu;
+      face_xy(0, ci, cj, gi, mxl, exl);
+      face_xy(0, ci + 1, cj, gi + 1, mxu, exu);
+      face_xy(1, ci, cj, gj, myl, eyl);
+      face_xy(1, ci, cj + 1, gj + 1, myu, eyu);
+      R mzl = R(0), ezl = R(0), mzu = R(0), ezu = R(0);
+      if (k > 0) {  // lower z face: donor k-1 (window slot 1) or k (slot 2)
+        if (zv0 > R(0))
+          flux(zv0, k - 1, m.nz, ihA[2], zr[0], zr[1], zr[2], ze[0], ze[1], ze[2], mzl, ezl);
+        else
+          flux(zv0, k, m.nz, ihA[2], zr[1], zr[2], zr[3], ze[1], ze[2], ze[3], mzl, ezl);
+      }
+      if (k + 1 < m.nz) {  // upper z face: donor k (slot 2) or k+1 (slot 3)
+        if (zv1 > R(0))
+          flux(zv1, k, m.nz, ihA[2], zr[1], zr[2], zr[3], ze[1], ze[2], ze[3], mzu, ezu);
+        else
+          flux(zv1, k + 1, m.nz, ihA[2], zr[2], zr[3], zr[4], ze[2], ze[3], ze[4], mzu, ezu);
+      }
+      const R netm = ((mxu - mxl) + (myu - myl)) + (mzu - mzl);
+      const R nete = ((exu - exl) + (eyu - eyl)) + (ezu - ezl);
+      const R M = rho * R(m.V0) - netm;
+      const R rn = rho - netm * R(m.iV0);
+      R epre = R(0);
+      if (!(M > R(0)) || !(rn > R(0)) || !isfinite(rn)) {
+        atomicOr(&ctl->status, SALE_FLAG_NUMERIC);
+      } else {
+        const R el = ze[2];
+        epre = el + (el * netm - nete) / M;
+      }
+      const int64_t c = cix + k * cpl;
+      t.mu[0][c] = mxl;
+      t.mu[1][c] = myl;
+      t.mu[2][c] = mzl;
+      nxt.rho[c] = rn;
+      t.M[c] = M;
+      t.epre[c] = epre;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+      zr[q] = zr[q + 1];
+      ze[q] = ze[q + 1];
+    }
+    zr[4] = nr;
+    ze[4] = ne;
+    zv0 = zv1;
+    zv1 = zv2;
   }
-  nxt.rho[c] = rn;
-  t.M[c] = M;
-  t.epre[c] = ep;
 }
 
 // ---- pass 3: node momentum and kinetic-energy remap ------------------------------------
@@ -451,7 +520,6 @@ template <typename R>
 hipError_t launch_remap2(const Mesh &m, Ctl *ctl, const Work<R> &w, int cur, hipStream_t s) {
   if (m.order != 2 || !w.r2.M) return hipErrorInvalidValue;
   const State<R> sc = w.s[cur], sn = w.s[1 - cur];
-  const dim3 gc((unsigned)blocks2(m.ncell)), b(TPB2);
   // tiles of the node and KE-fix passes: about 3072 blocks, at least 8
   // planes per z segment
   auto tiles = [](int cols, int rows, int planes, int tw, int th) {
@@ -467,8 +535,9 @@ hipError_t launch_remap2(const Mesh &m, Ctl *ctl, const Work<R> &w, int cur, hip
   };
   const Grid2 gnode = tiles(m.nx + 1, m.ny + 1, m.nz + 1, NTX, NTY);
   const Grid2 gf = tiles(m.nx, m.ny, m.nz, FTX, FTY);
-  hipLaunchKernelGGL(k_faces2<R>, gc, b, 0, s, m, ctl, w.geo, w.r2);
-  hipLaunchKernelGGL(k_cells2<R>, gc, b, 0, s, m, ctl, sc, sn, w.geo, w.r2);
+  const Grid2 gcell = tiles(m.nx, m.ny, m.nz, CTX, CTY);
+  hipLaunchKernelGGL(k_cells2<R>, dim3((unsigned)gcell.blocks()), dim3(CW2 * CH2), 0, s, m, ctl, sc, sn, w.geo, w.r2,
+                     gcell);
   hipLaunchKernelGGL(k_nodes2<R>, dim3((unsigned)gnode.blocks()), dim3(NW * NH), 0, s, m, ctl, sc, sn, w.geo, w.up,
                      w.vp, w.wp, w.r2, gnode);
   hipLaunchKernelGGL(k_fix2<R>, dim3((unsigned)gf.blocks()), dim3(FW * FH), 0, s, m, ctl, sc, sn, w.r2, gf);

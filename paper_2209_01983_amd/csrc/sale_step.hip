@@ -395,7 +395,7 @@ size_t workspace_bytes(const Mesh &m) {
   const size_t cR = align256((size_t)m.ncell * sizeof(R)), nR = align256((size_t)m.nnode * sizeof(R));
   const size_t sD = align256((size_t)(m.ncell > m.nnode ? m.ncell : m.nnode) * sizeof(double));
   // ctl | 2 states | u' | rho^L, e^L | 3 swept volumes | partials | scratch
-  const size_t r2 = m.order == 2 ? 8 * cR + nR : 0;  // second-order remap intermediates
+  const size_t r2 = m.order == 2 ? 5 * cR + nR : 0;  // second-order remap intermediates
   const size_t cD = align256((size_t)m.ncell * sizeof(double)), nD = align256((size_t)m.nnode * sizeof(double));
   const size_t lg = m.mode == 1 ? 6 * nD + 25 * cD : 0;  // positions x2, masses, corner forces
   return align256(sizeof(Ctl)) + 2 * (2 * cR + 3 * nR) + 3 * nR + 2 * cR + 3 * cR +
@@ -439,7 +439,6 @@ void layout(const Mesh &m, void *ws, Ctl **ctl, Work<R> *w) {
   w->r2 = Rem2<R>{};
   if (m.order == 2) {
     for (int a = 0; a < 3; a++) w->r2.mu[a] = takeR(cR);
-    for (int a = 0; a < 3; a++) w->r2.eps[a] = takeR(cR);
     w->r2.M = takeR(cR);
     w->r2.epre = takeR(cR);
     w->r2.dk = takeR(nR);
