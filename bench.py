@@ -443,8 +443,8 @@ def main():
     ms2, _, k2, _ = headline(n, a.steps, a.warmup, sale.SALE_FP64, tuned=False,
                              fixed=(shape64["rows_a"], shape64["rows_b"], shape64["target"]), order=2)
     out["remap_order2"] = {"value": cells * 1e3 / ms2, "unit": "cell-updates/s", "ms_per_step": ms2,
-                           "kernel_ms": {"k_begin": k2[0], "k_lagrange": k2[1], "remap (4 passes)": k2[2]},
-                           "precision": "fp64", "note": "limited linear donor values; direct multi-pass remap"}
+                           "kernel_ms": {"k_begin": k2[0], "k_lagrange": k2[1], "remap (3 passes)": k2[2]},
+                           "precision": "fp64", "note": "limited linear donor values; three z-marching tile passes"}
     if not a.quick:
         say("sod latency")
         out["latency"] = sod_latency(50)
