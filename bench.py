@@ -71,7 +71,7 @@ def parse():
                          "target); skips the autotuner")
     ap.add_argument("--precision-report", type=int, default=0, metavar="N",
                     help="also run the N^3 Sedov to t = 1 in FP64 and MIXED32 and report per-field errors")
-    ap.add_argument("--section", default="", choices=("", "latency", "sedov128", "noh128", "lagrange128"),
+    ap.add_argument("--section", default="", choices=("", "latency", "sedov128", "noh128", "lagrange128", "batched", "serving"),
                     help="run only this extra block and print its JSON (for profiling it)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run one plain device copy of 2 GiB (reference for HBM counters)")
@@ -387,7 +387,8 @@ def main():
 
     if a.section:
         block = {"latency": lambda: sod_latency(50), "sedov128": lambda: sedov128(3), "noh128": lambda: noh128(3),
-                 "lagrange128": lagrange128}[a.section]
+                 "lagrange128": lagrange128, "batched": batched,
+                 "serving": lambda: serving(a.serve_requests, a.serve_budget_gb)}[a.section]
         print(json.dumps({a.section: block()}), flush=True)
         return
     if a.copy_calibration:

@@ -151,11 +151,14 @@ constexpr int remap_lds_doubles() {
 //   P4  swept volumes of the faces of cell plane k-1 (they need delta on node
 //       planes k-1 and k only) and its compatible-energy work
 //   P5  V^L, rho^L, e^L of cell plane k-1; hand-off to remap_tile. It needs
-//       the neighbours' x/y swept volumes, so it runs after the next
-//       iteration's P1 barrier (they stay in LDS until that iteration's P4):
-//       three barriers per plane instead of four.
+//       the neighbours' x/y swept volumes: with DEFER it runs after the next
+//       iteration's P1 barrier (they stay in LDS until that iteration's P4),
+//       three barriers per plane instead of four; without, after a barrier
+//       of its own. The values it carries cost registers, which the
+//       multi-run kernels (run descriptors live too) do not have to spare.
+//       Both forms do the same arithmetic.
 // Returns true if a tangled cell was seen.
-template <typename R, int CH>
+template <typename R, int CH, bool DEFER = true>
 __device__ bool lagrange_tile(const RunArgs<R> &a, int b, double dtd, double *lds) {
   constexpr int CW = 32, NTH = CW * CH, TX = CW - 3, TY = CH - 3;
   const Mesh &m = a.m;
@@ -247,7 +250,7 @@ __device__ bool lagrange_tile(const RunArgs<R> &a, int b, double dtd, double *ld
     sU[2][cj][ci] = wn;
     __syncthreads();
     // ---- P5 of cell plane k-2 (its swept volumes are in LDS until P4) ----
-    finish(k - 2);
+    if constexpr (DEFER) finish(k - 2);
     // ---- P2 ----
     R ps = 0, mc = 0, imc = 0;
     {
@@ -361,20 +364,41 @@ __device__ bool lagrange_tile(const RunArgs<R> &a, int b, double dtd, double *ld
       sVX[cj][ci] = vx;
       sVY[cj][ci] = vy;
     }
-    // P5 of this plane runs after the next plane's first barrier
-    if (own_cell && cp >= Z0 && cp < Z1) {
-      h_el = (double)e1 - (double)ps1 * work / (double)m1;
-      h_vz = dvz_lo;
-      h_m = m1;
+    if constexpr (DEFER) {  // P5 of this plane after the next plane's first barrier
+      if (own_cell && cp >= Z0 && cp < Z1) {
+        h_el = (double)e1 - (double)ps1 * work / (double)m1;
+        h_vz = dvz_lo;
+        h_m = m1;
+      }
+    } else {  // P5 of this plane now (the same arithmetic as finish())
+      __syncthreads();
+      settle(fu), settle(fv), settle(fw), settle(frho), settle(fe);  // loads issued in P1
+      if (own_cell && cp >= Z0 && cp < Z1) {
+        const double VL =
+            m.V0 + (((sVX[cj][ci + 1] - sVX[cj][ci]) + (sVY[cj + 1][ci] - sVY[cj][ci])) + (dvz_up - dvz_lo));
+        double rl = 0.0;
+        if (!(VL > 0.0))
+          tangle = true;
+        else
+          rl = (double)m1 / VL;
+        const uint32_t oR = cix * (uint32_t)sizeof(R);
+        plane_at<R>(a.geo.rl, cpl, cp, oR) = R(rl);
+        plane_at<R>(a.geo.el, cpl, cp, oR) = R((double)e1 - (double)ps1 * work / (double)m1);
+        plane_at<R>(a.geo.dvx, cpl, cp, oR) = R(sVX[cj][ci]);
+        plane_at<R>(a.geo.dvy, cpl, cp, oR) = R(sVY[cj][ci]);
+        plane_at<R>(a.geo.dvz, cpl, cp, oR) = R(dvz_lo);
+      }
     }
     dvz_lo = dvz_up;
     ps1 = ps;
     e1 = e_k;
     m1 = mc;
-    settle(fu), settle(fv), settle(fw), settle(frho), settle(fe);  // loads issued in P1
+    if constexpr (DEFER) settle(fu), settle(fv), settle(fw), settle(frho), settle(fe);  // loads issued in P1
   }
-  __syncthreads();
-  finish(Z1 - 1);
+  if constexpr (DEFER) {
+    __syncthreads();
+    finish(Z1 - 1);
+  }
   return tangle;
 }
 
