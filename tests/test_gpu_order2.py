@@ -1,9 +1,10 @@
 """GPU parity of the second-order remap (remap_order 2) against the FP64
 oracle's second-order remap, through the C ABI: per field max |gpu - oracle|
 / scale <= 1e-12 (velocity components against the largest speed component,
-as for the first-order path) on ragged random meshes, the Sod tube and a
-Sedov trajectory; bitwise determinism, restart and fixed point; MIXED32 at
-its stated bar; the pool refuses order 2."""
+as for the first-order path) on ragged random meshes, the Sod tube, a
+Sedov trajectory and single steps on the full 320^3 and 128^3 Sedov meshes;
+bitwise determinism, restart and fixed point; MIXED32 at its stated bar;
+the pool refuses order 2."""
 import numpy as np
 import pytest
 
@@ -78,6 +79,28 @@ def test_order2_sedov_trajectory_matches_oracle_and_conserves():
     m1, E1 = r.totals()
     assert abs(m1 - m0) / m0 < 1e-13 and abs(E1 - E0) / E0 < 1e-12
     assert r.state()[1] == s.step
+
+
+def test_order2_sedov_320_single_step_bench_configuration():
+    """The benchmark's second-order configuration: the full 320^3 Sedov mesh
+    (several tiles and z segments of every pass), one oracle step from a
+    developed GPU state against one GPU step, and the 128^3 mesh after 200
+    steps (a wider blast, ragged last tiles: 129 node columns over tiles of
+    28 x 12)."""
+    for n, steps in ((320, 30), (128, 200)):
+        cfg = cfg2(n, n, n, hi=(1.2, 1.2, 1.2), t_end=1.0)
+        say("order2 sedov", n, "GPU steps", steps)
+        r = sale.SaleRun(cfg, sale.sedov_problem())
+        assert r.run(max_steps=steps) == sale.SALE_OK
+        t, nstep, _, _ = r.state()
+        s = oracle_state(r.fields(), t=t, step=nstep)
+        say("order2 sedov", n, "oracle step")
+        assert orc.Oracle(grid_of(cfg)).step(s)[0] == orc.OK
+        r.step()
+        err = assert_parity(r.fields(), s, what=f"order2 {n}^3 step {nstep + 1}")
+        assert r.state()[0] == pytest.approx(s.t, rel=1e-14)
+        say("order2 sedov", n, "errors", err)
+        r.close()
 
 
 def test_order2_determinism_restart_and_fixed_point():
