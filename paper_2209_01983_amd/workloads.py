@@ -107,13 +107,16 @@ Served = collections.namedtuple("Served", "index arrival admitted finished slot 
 
 
 def serve(trace, precision, budget_bytes, max_runs=512, slice_steps=25, keep=None, fetch=True,
-          clock=time.perf_counter, sleep=time.sleep, max_cells=None):
+          clock=time.perf_counter, sleep=time.sleep, max_cells=None, order="fifo"):
     """Continuous-batching server over a request trace (dicts with arrival
     time in s, kind, n, steps and the problem parameters).
 
-    Requests enter a FIFO queue at their arrival time; the head is admitted
-    into the pool whenever a slot and an arena range of the HBM budget are
-    free (admission refuses otherwise, and the head waits) and, with
+    Requests enter a queue at their arrival time; its head is admitted into
+    the pool whenever a slot and an arena range of the HBM budget are free
+    (admission refuses otherwise, and the head waits). The queue is in
+    arrival order (`order="fifo"`) or, with `order="sjf"`, in order of the
+    work a request asks for (cells x steps, shortest first; ties by arrival),
+    which cuts the median latency when requests wait. With
     `max_cells`, while the admitted runs hold fewer cells than that (a cap on
     how many runs share the GPU at once: fewer runs in flight finish sooner
     each, as long as they still fill the chip). Admitted runs
@@ -126,6 +129,8 @@ def serve(trace, precision, budget_bytes, max_runs=512, slice_steps=25, keep=Non
     Returns (list of Served, stats dict)."""
     import numpy as np
 
+    if order not in ("fifo", "sjf"):
+        raise ValueError(f"order must be 'fifo' or 'sjf', not {order!r}")
     pool = sale.Pool(budget_bytes, max_runs=max_runs, precision=precision)
     pending = collections.deque(enumerate(trace))
     queue = collections.deque()
@@ -137,8 +142,12 @@ def serve(trace, precision, budget_bytes, max_runs=512, slice_steps=25, keep=Non
     launches = 0
     while pending or queue or active:
         now = clock() - t_start
+        arrived = False
         while pending and pending[0][1]["arrival"] <= now:
             queue.append(pending.popleft())
+            arrived = True
+        if arrived and order == "sjf":
+            queue = collections.deque(sorted(queue, key=lambda q: (cells(q[1]) * q[1]["steps"], q[0])))
         while queue:
             i, req = queue[0]
             if max_cells is not None and active and active_cells + cells(req) > max_cells:
@@ -182,5 +191,5 @@ def serve(trace, precision, budget_bytes, max_runs=512, slice_steps=25, keep=Non
              "latency_p50_s": float(np.percentile(lat, 50)), "latency_p99_s": float(np.percentile(lat, 99)),
              "queue_p50_s": float(np.percentile(qd, 50)), "queue_p99_s": float(np.percentile(qd, 99)),
              "launches": launches, "slice_steps": slice_steps, "budget_bytes": budget_bytes,
-             "max_cells": max_cells}
+             "max_cells": max_cells, "order": order}
     return sorted(out, key=lambda s: s.index), stats

@@ -1,6 +1,7 @@
-"""Host logic of the continuous-batching server (no GPU): FIFO admission
-under a budget, slicing, completion, release and latency accounting, with
-the pool replaced by a stand-in that only counts steps."""
+"""Host logic of the continuous-batching server (no GPU): FIFO and
+shortest-job-first admission under a budget, slicing, completion, release
+and latency accounting, with the pool replaced by a stand-in that only
+counts steps."""
 import pytest
 
 from paper_2209_01983_amd import sale, workloads
@@ -83,6 +84,23 @@ def test_fifo_admission_under_budget_and_latency_accounting(monkeypatch):
     assert served[2].admitted > served[2].arrival  # waited for memory
     assert st["requests"] == 5 and st["latency_p99_s"] >= st["latency_p50_s"] > 0
     assert st["cell_updates_per_s"] > 0
+
+
+def test_shortest_job_first_admits_the_smallest_waiting_request(monkeypatch):
+    monkeypatch.setattr(sale, "Pool", CountingPool)
+    CountingPool.log = []
+    # all arrive at once; the budget holds one 4^3 run or several small ones
+    tr = trace_of([(4, 20), (4, 30), (2, 50), (3, 5), (2, 10)], gap=0.0)
+    clk = FakeClock()
+    served, st = workloads.serve(tr, sale.SALE_FP64, 64 + 10, max_runs=4, slice_steps=5, clock=clk,
+                                 sleep=clk.sleep, order="sjf")
+    admitted = [(e[2]) for e in CountingPool.log]
+    # work = cells x steps: 2^3*10=80 < 3^3*5=135 < 2^3*50=400 < 4^3*20 < 4^3*30
+    assert admitted == [2, 3, 2, 4, 4]
+    assert all(s.fields["steps"] == tr[s.index]["steps"] for s in served)
+    assert st["order"] == "sjf"
+    with pytest.raises(ValueError):
+        workloads.serve(tr, sale.SALE_FP64, 1000, clock=clk, sleep=clk.sleep, order="lifo")
 
 
 def test_idle_server_sleeps_until_the_next_arrival(monkeypatch):
