@@ -19,13 +19,14 @@ def small_trace():
     return tr
 
 
-@pytest.mark.parametrize("precision", [sale.SALE_FP64, sale.SALE_MIXED32])
-def test_served_results_equal_alone_results(precision):
-    say("serving equality, precision", precision)
+@pytest.mark.parametrize("precision,order", [(sale.SALE_FP64, "fifo"), (sale.SALE_MIXED32, "fifo"),
+                                             (sale.SALE_MIXED32, "sjf")])
+def test_served_results_equal_alone_results(precision, order):
+    say("serving equality, precision", precision, order)
     trace = small_trace()
     per = [sale.sale_workspace_bytes(workloads.request_problem(r, precision)[0]) for r in trace]
     budget = 3 * max(per) + (1 << 20)   # a few runs at a time: admission has to wait
-    served, st = workloads.serve(trace, precision, budget, max_runs=8, slice_steps=7)
+    served, st = workloads.serve(trace, precision, budget, max_runs=8, slice_steps=7, order=order)
     assert [s.index for s in served] == list(range(len(trace)))
     assert st["requests"] == len(trace) and st["launches"] >= 2
     assert any(s.admitted > s.arrival + 1e-3 for s in served), "no request ever waited for memory"
