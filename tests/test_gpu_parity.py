@@ -317,6 +317,25 @@ def test_mixed32_single_steps_vs_fp64_oracle():
     say("mixed32 5-step errors", err)
 
 
+def test_mixed32_sedov_320_single_step_vs_fp64_oracle():
+    """MIXED32 in the benchmark's configuration: the full 320^3 Sedov mesh,
+    one GPU step from the MIXED32 run's developed state against the FP64
+    oracle's step from the same (widened) state, at the single-step bar."""
+    cfg = mixed_cfg(320, 320, 320, hi=(1.2, 1.2, 1.2), t_end=1.0)
+    say("mixed32 sedov 320^3: 30 GPU steps")
+    r = sale.SaleRun(cfg, sale.sedov_problem())
+    assert r.run(max_steps=30) == sale.SALE_OK
+    t, steps, _, _ = r.state()
+    s = oracle_state(r.fields(), t=t, step=steps)
+    assert orc.Oracle(grid_of(cfg)).step(s)[0] == orc.OK
+    r.step()
+    err = errors(r.fields(), s)
+    say("mixed32 320^3 errors", err)
+    assert max(err.values()) <= TOL32_STEP, err
+    assert r.state()[0] == pytest.approx(s.t, rel=1e-6)
+    r.close()
+
+
 def test_mixed32_sod_tube_vs_fp64_oracle():
     cfg = mixed_cfg(64, 4, 4, hi=(1.0, 0.0625, 0.0625), t_end=0.2)
     r = sale.SaleRun(cfg, sale.sod_problem())
