@@ -203,7 +203,7 @@ __global__ __launch_bounds__(CW2 * CH2) void k_cells2(Mesh m, Ctl *ctl, State<R>
   }
 }
 
-// ---- pass 3: node momentum and kinetic-energy remap ------------------------------------
+// ---- pass 2: node momentum and kinetic-energy remap ------------------------------------
 // A 32 x 16 tile of node columns (halo 2 on each side: the limited profiles
 // along x and y reach two nodes out) marched along z over one segment. For
 // node plane k the LDS holds u' of the plane and the face data of cell
@@ -431,7 +431,7 @@ __global__ __launch_bounds__(NW * NH, 4) void k_nodes2(Mesh m, Ctl *ctl, State<R
   }
 }
 
-// ---- pass 4: kinetic-energy fix, new energy, next signal speed ------------------------
+// ---- pass 3: kinetic-energy fix, new energy, next signal speed ------------------------
 // A 32 x 16 tile of node columns marched along z over one segment: each
 // node plane's u^{n+1}, v, w and KE defect are read once into LDS, a cell
 // column forms its lower-plane half (partial defect sum, largest |u|^2,
