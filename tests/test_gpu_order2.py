@@ -127,6 +127,42 @@ def test_order2_determinism_restart_and_fixed_point():
         assert np.array_equal(fd[k], q[k]), k
 
 
+def test_order2_done_steps_and_error_codes():
+    """After t_end a second-order step changes nothing (each pass carries its
+    part of the state across) and a later end time continues the run; a
+    tangled predictor volume is flagged as on the oracle's second-order path;
+    a flagged run stops."""
+    cfg = cfg2(16, 5, 3, hi=(1.0, 5 / 16, 3 / 16), t_end=0.05)
+    r = sale.SaleRun(cfg, sale.sod_problem())
+    assert r.run() == sale.SALE_DONE
+    f0, st0 = r.fields(), r.state()
+    r.step(3)
+    f1 = r.fields()
+    assert r.state() == st0 and st0[0] == 0.05
+    for k in FIELDS:
+        assert np.array_equal(f0[k], f1[k]), k
+    assert r.run(t_end=0.1) == sale.SALE_DONE and r.state()[0] == 0.1
+    # forced predictor tangle: CFL 0.99, no viscosity, converging centre cell
+    cfg = cfg2(3, 3, 3, cfl=0.99, c_quad=0.0, c_lin=0.0, t_end=1.0)
+    g = grid_of(cfg)
+    s = orc.empty_state(g)
+    s.rho[...] = 1.0
+    s.e[...] = 1e-8
+    for c in (1, 2):
+        for b in (1, 2):
+            for a in (1, 2):
+                s.u[c, b, a] = -10.0 * (2 * (a - 1) - 1)
+                s.v[c, b, a] = -10.0 * (2 * (b - 1) - 1)
+                s.w[c, b, a] = -10.0 * (2 * (c - 1) - 1)
+    assert orc.Oracle(g).step(s.copy())[0] == orc.ETANGLE
+    r = user_run(cfg, s.fields())
+    r.step()
+    rc, flags = r.status()
+    assert rc == sale.SALE_ETANGLE and flags & sale.SALE_FLAG_TANGLE
+    t, n, _, _ = r.state()
+    assert r.run() == sale.SALE_ETANGLE and r.state()[:2] == (t, n)
+
+
 def test_order2_mixed32_sod_within_bar():
     cfg = cfg2(64, 4, 4, hi=(1.0, 0.0625, 0.0625), t_end=0.2, precision=sale.SALE_MIXED32)
     r = sale.SaleRun(cfg, sale.sod_problem())
