@@ -383,6 +383,10 @@ int sale_init(const sale_config *cfg, const sale_problem *prob, void *d_ws, size
   if (!x) return SALE_ENOMEM;
   x->cfg = *cfg;
   x->m = m;
+  // a mesh at most 4 cells across in y fits one row of 8-row remap tiles,
+  // whose 4-wave blocks pass their barriers sooner (a Sod tube 64x4x4 runs
+  // 3% faster)
+  if (m.ny <= 4) x->L.rows_b = 8;
   x->stream = (hipStream_t)hip_stream;
   x->ws = d_ws;
   x->ws_bytes = ws_bytes;
