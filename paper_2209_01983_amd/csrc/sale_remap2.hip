@@ -207,18 +207,21 @@ __global__ __launch_bounds__(CW2 * CH2) void k_cells2(Mesh m, Ctl *ctl, State<R>
 // A 32 x 16 tile of node columns (halo 2 on each side: the limited profiles
 // along x and y reach two nodes out) marched along z over one segment. For
 // node plane k the LDS holds u' of the plane and the face data of cell
-// planes k-1 and k (x/y mass fluxes and swept volumes, the z faces' lower +
-// upper sums, old and new cell masses; two buffers by plane parity); u' of
-// node planes k-2..k+2 (the z profiles) is carried in registers. Each input
-// value is read from memory once per tile.
+// planes k-1 and k: x/y mass fluxes and swept volumes and the old and new
+// cell masses as per-column sums of the two planes (every stencil adds both
+// planes), the z faces' lower + upper sums of plane k (those of plane k-1
+// are carried in registers, formed in the previous pass). u' of node planes
+// k-2..k+2 (the z profiles) is carried in registers. Each input value is
+// read from memory once per tile.
 constexpr int NW = 32, NH = 16, NTX = NW - 4, NTY = NH - 4;
 
 template <typename R>
 __global__ __launch_bounds__(NW * NH, 4) void k_nodes2(Mesh m, Ctl *ctl, State<R> cur, State<R> nxt, Geo<R> geo,
                                                    const R *up, const R *vp, const R *wp, Rem2<R> t, Grid2 g) {
   enum { MX, MY, VX, VY, SZ, VZ, MO, MN, NCP };
-  __shared__ R LU[3][NH][NW];         // u', v', w' of node plane k
-  __shared__ R LC[2][NCP][NH][NW];    // cell planes k-1, k (buffer = plane & 1)
+  __shared__ R LU[3][NH][NW];    // u', v', w' of node plane k
+  __shared__ R LC[NCP][NH][NW];  // MX..VY, MO, MN: cell planes k-1 + k; SZ, VZ: plane k
+  __shared__ R LP[6][NH][NW];    // the thread's own column at cell plane k-1 (private)
   int tx, ty, seg;
   tile_of(g, blockIdx.x, tx, ty, seg);
   const int ci = threadIdx.x % NW, cj = threadIdx.x / NW;
@@ -279,36 +282,55 @@ __global__ __launch_bounds__(NW * NH, 4) void k_nodes2(Mesh m, Ctl *ctl, State<R
   };
   const int K0 = Z0 - 1;  // first pass: sums of cell plane Z0-1 for node plane Z0
   for (int q = 0; q < 5; q++) node_load(K0 - 2 + q, zu[q], zv[q], zw[q]);
+  cell_load(K0 - 1);
+  LP[0][cj][ci] = f_mx;
+  LP[1][cj][ci] = f_my;
+  LP[2][cj][ci] = f_vx;
+  LP[3][cj][ci] = f_vy;
+  LP[4][cj][ci] = f_mo;
+  LP[5][cj][ci] = f_mn;
   cell_load(K0);
   R z_m0, z_v0;
   zface_load(K0, z_m0, z_v0);
   zface_load(K0 + 1, z_m1, z_v1);
 
+  // the z dual faces below node plane k (those of cell plane k-1), carried
+  // from the previous pass
+  R zs_m = R(0), zs_v = R(0);
   for (int k = K0; k < NZ1; k++) {
-    R(*const C)[NH][NW] = LC[k & 1];        // cell plane k
-    R(*const Cm)[NH][NW] = LC[(k + 1) & 1];  // cell plane k-1 (written by the previous pass)
+    R(*const C)[NH][NW] = LC;
     LU[0][cj][ci] = zu[2];
     LU[1][cj][ci] = zv[2];
     LU[2][cj][ci] = zw[2];
-    C[MX][cj][ci] = f_mx;
-    C[MY][cj][ci] = f_my;
-    C[VX][cj][ci] = f_vx;
-    C[VY][cj][ci] = f_vy;
+    // every stencil below sums a field over the cells of planes k-1 and k
+    // around the node: the two planes are added per cell column here
+    C[MX][cj][ci] = LP[0][cj][ci] + f_mx;
+    C[MY][cj][ci] = LP[1][cj][ci] + f_my;
+    C[VX][cj][ci] = LP[2][cj][ci] + f_vx;
+    C[VY][cj][ci] = LP[3][cj][ci] + f_vy;
     C[SZ][cj][ci] = z_m0 + z_m1;  // lower + upper z face of the cell
     C[VZ][cj][ci] = z_v0 + z_v1;
-    C[MO][cj][ci] = f_mo;
-    C[MN][cj][ci] = f_mn;
+    C[MO][cj][ci] = LP[4][cj][ci] + f_mo;
+    C[MN][cj][ci] = LP[5][cj][ci] + f_mn;
+    LP[0][cj][ci] = f_mx;
+    LP[1][cj][ci] = f_my;
+    LP[2][cj][ci] = f_vx;
+    LP[3][cj][ci] = f_vy;
+    LP[4][cj][ci] = f_mo;
+    LP[5][cj][ci] = f_mn;
     // next pass: cell plane k+1, z faces of k+2, node plane k+3
     R nu, nv, nw;
     cell_load(k + 1);
     zface_load(k + 2, z_m2, z_v2);
     node_load(k + 3, nu, nv, nw);
     __syncthreads();
+    // sums over the 4 cell columns around the node (zero where absent)
+    auto c4 = [&](R(*P)[NH][NW], int s) {
+      return ((P[s][cj - 1][ci - 1] + P[s][cj - 1][ci]) + P[s][cj][ci - 1]) + P[s][cj][ci];
+    };
+    // the z dual faces above node plane k: those of the 4 cells of plane k
+    const R za_m = own ? R(0.125) * c4(C, SZ) : R(0), za_v = own ? R(0.125) * c4(C, VZ) : R(0);
     if (own && k >= Z0) {
-      // sums over the 4 cells of cell planes k-1 and k around the node (zero where absent)
-      auto c4 = [&](R(*P)[NH][NW], int s) {
-        return ((P[s][cj - 1][ci - 1] + P[s][cj - 1][ci]) + P[s][cj][ci - 1]) + P[s][cj][ci];
-      };
       // x edges: cells (i, j-1..j) (outflow) and (i-1, j-1..j) (inflow), lower + upper face each
       auto xo = [&](R(*P)[NH][NW], int s) {
         return (P[s][cj - 1][ci] + P[s][cj - 1][ci + 1]) + (P[s][cj][ci] + P[s][cj][ci + 1]);
@@ -324,7 +346,7 @@ __global__ __launch_bounds__(NW * NH, 4) void k_nodes2(Mesh m, Ctl *ctl, State<R
         return (P[s][cj - 1][ci - 1] + P[s][cj][ci - 1]) + (P[s][cj - 1][ci] + P[s][cj][ci]);
       };
       {
-        const R mp = R(0.125) * (c4(Cm, MO) + c4(C, MO)), mn = R(0.125) * (c4(Cm, MN) + c4(C, MN));
+        const R mp = R(0.125) * (c4(C, MO)), mn = R(0.125) * (c4(C, MN));
         const R u1 = zu[2], v1 = zv[2], w1 = zw[2];
         R P0 = mp * u1, P1 = mp * v1, P2 = mp * w1;
         R K = R(0.5) * mp * (u1 * u1 + v1 * v1 + w1 * w1);
@@ -355,13 +377,13 @@ __global__ __launch_bounds__(NW * NH, 4) void k_nodes2(Mesh m, Ctl *ctl, State<R
           flow(phi, ud, vd, wd, sgn);
         };
         if (gi + 1 <= m.nx)
-          inplane(0, m.nx, gi, R(0.125) * (xo(Cm, MX) + xo(C, MX)), R(0.125) * (xo(Cm, VX) + xo(C, VX)), R(-1));
+          inplane(0, m.nx, gi, R(0.125) * (xo(C, MX)), R(0.125) * (xo(C, VX)), R(-1));
         if (gi >= 1)
-          inplane(0, m.nx, gi - 1, R(0.125) * (xi(Cm, MX) + xi(C, MX)), R(0.125) * (xi(Cm, VX) + xi(C, VX)), R(1));
+          inplane(0, m.nx, gi - 1, R(0.125) * (xi(C, MX)), R(0.125) * (xi(C, VX)), R(1));
         if (gj + 1 <= m.ny)
-          inplane(1, m.ny, gj, R(0.125) * (yo(Cm, MY) + yo(C, MY)), R(0.125) * (yo(Cm, VY) + yo(C, VY)), R(-1));
+          inplane(1, m.ny, gj, R(0.125) * (yo(C, MY)), R(0.125) * (yo(C, VY)), R(-1));
         if (gj >= 1)
-          inplane(1, m.ny, gj - 1, R(0.125) * (yi(Cm, MY) + yi(C, MY)), R(0.125) * (yi(Cm, VY) + yi(C, VY)), R(1));
+          inplane(1, m.ny, gj - 1, R(0.125) * (yi(C, MY)), R(0.125) * (yi(C, VY)), R(1));
         // z edges: the column's own u' at node planes k-2..k+2 (window slot 2 = plane k)
         auto zedge = [&](int s, R phi, R dv, R sgn) {  // lower node in window slot s
           const bool lower = phi > R(0);
@@ -392,8 +414,8 @@ __global__ __launch_bounds__(NW * NH, 4) void k_nodes2(Mesh m, Ctl *ctl, State<R
         };
         // z edges: the dual face between node planes k and k+1 is that of the
         // 4 cells of plane k, the one between k-1 and k that of plane k-1
-        if (k + 1 <= m.nz) zedge(2, R(0.125) * c4(C, SZ), R(0.125) * c4(C, VZ), R(-1));
-        if (k >= 1) zedge(1, R(0.125) * c4(Cm, SZ), R(0.125) * c4(Cm, VZ), R(1));
+        if (k + 1 <= m.nz) zedge(2, za_m, za_v, R(-1));
+        if (k >= 1) zedge(1, zs_m, zs_v, R(1));
         R un = R(0), vn = R(0), wn = R(0), dk = R(0);
         if (!(mn > R(0))) {
           atomicOr(&ctl->status, SALE_FLAG_NUMERIC);
@@ -414,6 +436,8 @@ __global__ __launch_bounds__(NW * NH, 4) void k_nodes2(Mesh m, Ctl *ctl, State<R
         t.dk[q] = dk;
       }
     }
+    zs_m = za_m;
+    zs_v = za_v;
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < 4; q++) {
