@@ -544,14 +544,14 @@ template <typename R>
 hipError_t launch_remap2(const Mesh &m, Ctl *ctl, const Work<R> &w, int cur, hipStream_t s) {
   if (m.order != 2 || !w.r2.M) return hipErrorInvalidValue;
   const State<R> sc = w.s[cur], sn = w.s[1 - cur];
-  // tiles of the node and KE-fix passes: about 3072 blocks, at least 8
+  // tiles of the three passes: about 6144 blocks, at least 8
   // planes per z segment
   auto tiles = [](int cols, int rows, int planes, int tw, int th) {
     Grid2 g;
     g.tx = (cols + tw - 1) / tw;
     g.ty = (rows + th - 1) / th;
     const int maxseg = planes / 8 > 1 ? planes / 8 : 1;
-    int nseg = (3072 + g.tx * g.ty / 2) / (g.tx * g.ty);
+    int nseg = (6144 + g.tx * g.ty / 2) / (g.tx * g.ty);
     nseg = nseg < 1 ? 1 : nseg > maxseg ? maxseg : nseg;
     g.seglen = (planes + nseg - 1) / nseg;
     g.nseg = (planes + g.seglen - 1) / g.seglen;
