@@ -112,9 +112,9 @@ Mesh make_mesh(const sale_config *c) {
   m.hyz = m.dy * m.dz;
   m.hzx = m.dz * m.dx;
   m.hxy = m.dx * m.dy;
-  m.hdx = 0.5 * m.dx;
-  m.hdy = 0.5 * m.dy;
-  m.hdz = 0.5 * m.dz;
+  m.edx = 0.125 * m.dx;
+  m.edy = 0.125 * m.dy;
+  m.edz = 0.125 * m.dz;
   m.ncell = (int64_t)c->nx * c->ny * c->nz;
   m.order = c->remap_order == 2 ? 2 : 1;
   m.mode = c->mode == SALE_LAGRANGIAN ? 1 : 0;

@@ -23,37 +23,39 @@ __device__ __forceinline__ bool cell_in(const Mesh &m, int i, int j, int k) {
 // Exact volume swept by a rectangular face (edge lengths h1 along its first
 // tangent s, h2 along its second t; tangents cyclic after the normal) whose
 // corners (s,t) = (0,0), (1,0), (0,1), (1,1) move by d0..d3 (components:
-// normal, t1, t2). With delta(s,t) = A + B s + C t + E s t the swept volume is
+// normal xi, t1 eta, t2 zeta). The swept volume is
 //   h1 h2 <xi> + h1/2 <xi zeta_t - zeta xi_t> + h2/2 <xi eta_s - eta xi_s>
-//   + 1/3 <delta . (delta_s x delta_t)>,   <.> = integral over [0,1]^2.
-// The two middle brackets reduce to 1D integrals along the edges t = 0 and
-// s = 0 (their s t terms cancel) and the triple product integrates to
-// A.(B x C) + 1/2 A.((B - C) x E) + 1/4 C.(B x E).
-// h12 = h1 h2, hh1 = h1 / 2, hh2 = h2 / 2.
+//   + 1/3 <delta . (delta_s x delta_t)>,   <.> = integral over [0,1]^2,
+// and for the bilinear delta each bracket has a closed form in the corners:
+//   <xi>                        = (d0 + d1 + d2 + d3)_xi / 4
+//   <xi zeta_t - zeta xi_t>     = [m0 x m1]_(xi,zeta) / 4 + [b x e]_(xi,zeta) / 12
+//   <xi eta_s - eta xi_s>       = [n0 x n1]_(xi,eta) / 4 + [c x e]_(xi,eta) / 12
+//   <delta . (delta_s x delta_t)> = (d0 + d1 + d2 + d3) . ((d3 - d0) x (d2 - d1)) / 8
+// with the edge sums m0 = d0 + d1, m1 = d2 + d3 (edges along s), n0 = d0 + d2,
+// n1 = d1 + d3 (edges along t), the edge differences b = d1 - d0, c = d2 - d0,
+// the twist e = d3 - d2 - d1 + d0, and [p x q]_(a,b) = p_a q_b - p_b q_a. (The
+// last line is the cone volume of a bilinear patch through its diagonals.)
+// q12 = h1 h2 / 4, e1 = h1 / 8, e2 = h2 / 8.
 template <typename R>
 __device__ __forceinline__ R swept_volume(const R d0[3], const R d1[3], const R d2[3], const R d3[3],
-                                          R h12, R hh1, R hh2) {
-  R A[3], B[3], C[3], E[3];
-#pragma unroll
-  for (int a = 0; a < 3; a++) {
-    A[a] = d0[a];
-    B[a] = d1[a] - d0[a];
-    C[a] = d2[a] - d0[a];
-    E[a] = (d3[a] - d1[a]) - C[a];
-  }
-  const R half = R(0.5), third = R(1) / R(3), quarter = R(0.25);
-  const R t0 = h12 * (quarter * ((d0[0] + d1[0]) + (d2[0] + d3[0])));
-  const R i1 = (A[0] * C[2] + half * (A[0] * E[2] + B[0] * C[2]) + third * B[0] * E[2]) -
-               (A[2] * C[0] + half * (A[2] * E[0] + B[2] * C[0]) + third * B[2] * E[0]);
-  const R i2 = (A[0] * B[1] + half * (A[0] * E[1] + C[0] * B[1]) + third * C[0] * E[1]) -
-               (A[1] * B[0] + half * (A[1] * E[0] + C[1] * B[0]) + third * C[1] * E[0]);
-  const R BC0 = B[1] * C[2] - B[2] * C[1], BC1 = B[2] * C[0] - B[0] * C[2], BC2 = B[0] * C[1] - B[1] * C[0];
-  const R D0 = B[0] - C[0], D1 = B[1] - C[1], D2 = B[2] - C[2];
-  const R DE0 = D1 * E[2] - D2 * E[1], DE1 = D2 * E[0] - D0 * E[2], DE2 = D0 * E[1] - D1 * E[0];
-  const R BE0 = B[1] * E[2] - B[2] * E[1], BE1 = B[2] * E[0] - B[0] * E[2], BE2 = B[0] * E[1] - B[1] * E[0];
-  const R trip = (A[0] * BC0 + A[1] * BC1 + A[2] * BC2) + half * (A[0] * DE0 + A[1] * DE1 + A[2] * DE2) +
-                 quarter * (C[0] * BE0 + C[1] * BE1 + C[2] * BE2);
-  return t0 + hh1 * i1 + hh2 * i2 + third * trip;
+                                          R q12, R e1, R e2) {
+  const R third = R(1) / R(3);
+  // (xi, zeta) brackets
+  const R m0x = d0[0] + d1[0], m1x = d2[0] + d3[0], m0z = d0[2] + d1[2], m1z = d2[2] + d3[2];
+  const R bx = d1[0] - d0[0], bz = d1[2] - d0[2];
+  const R ex = (d3[0] - d2[0]) - bx, ez = (d3[2] - d2[2]) - bz;
+  const R Sx = m0x + m1x, Sz = m0z + m1z;
+  R v = q12 * Sx + e1 * ((m0x * m1z - m0z * m1x) + third * (bx * ez - bz * ex));
+  // (xi, eta) brackets
+  const R n0x = d0[0] + d2[0], n1x = d1[0] + d3[0], n0y = d0[1] + d2[1], n1y = d1[1] + d3[1];
+  const R ey = (d3[1] - d2[1]) - (d1[1] - d0[1]);
+  const R Sy = n0y + n1y;
+  v += e2 * ((n0x * n1y - n0y * n1x) + third * ((d2[0] - d0[0]) * ey - (d2[1] - d0[1]) * ex));
+  // cone volume through the diagonals
+  const R gx = d3[0] - d0[0], gy = d3[1] - d0[1], gz = d3[2] - d0[2];
+  const R fx = d2[0] - d1[0], fy = d2[1] - d1[1], fz = d2[2] - d1[2];
+  const R trip = (Sx * (gy * fz - gz * fy) + Sy * (gz * fx - gx * fz)) + Sz * (gx * fy - gy * fx);
+  return v + third * (R(0.125) * trip);
 }
 
 // a * b rounded on its own: the empty statement hides the product from the

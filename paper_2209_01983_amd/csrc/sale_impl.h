@@ -23,7 +23,7 @@ struct Mesh {
   double gm1, ggm1;          // gamma - 1, gamma (gamma - 1)
   double cq4h;               // 4 c_quad h
   double hyz, hzx, hxy;      // face areas dy dz, dz dx, dx dy
-  double hdx, hdy, hdz;      // half spacings dx/2, dy/2, dz/2
+  double edx, edy, edz;      // eighth spacings dx/8, dy/8, dz/8 (swept volumes)
   int64_t ncell, nnode;
   int order;                 // remap order: 1 donor cell, 2 limited linear
   int mode;                  // 0 Eulerian (Lagrange + remap), 1 pure Lagrangian (mesh moves)
@@ -62,11 +62,13 @@ struct State {
 };
 
 // Per-cell results of the Lagrangian phase handed from the first step kernel
-// to the second: rho^L, e^L and the swept volumes of the cell's three lower
-// faces (x face at its lower x side, etc.; zero on the domain boundary). A
-// cell's upper face is its +axis neighbour's lower face, or a wall. Swept
-// volumes are computed in FP64 in both precisions and handed over in the bulk
-// type R, the type the remap's fluxes use them in.
+// to the second: e^L and the swept volumes of the cell's three lower faces (x
+// face at its lower x side, etc.; zero on the domain boundary). A cell's
+// upper face is its +axis neighbour's lower face, or a wall; the remap forms
+// V^L and rho^L from the six. Swept volumes are computed in FP64 in both
+// precisions and handed over in the bulk type R, the type the remap's fluxes
+// use them in. rho^L (second-order remap only, null otherwise) is formed by a
+// pass of its own for the second-order passes, which read it with a halo.
 template <typename R>
 struct Geo {
   R *rl, *el;

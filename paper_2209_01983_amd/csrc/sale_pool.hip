@@ -42,11 +42,6 @@ constexpr int waves_of_lock() { return CH == 12 || CH == 24 ? 3 : 4; }
 // blocks per CU
 template <typename R>
 constexpr int waves_of_lock_remap() { return sizeof(R) == 4 && CH == 16 ? 6 : waves_of_lock(); }
-// Lagrange tiles of the multi-run kernels: the deferred P5 (one barrier
-// fewer per plane) pays in FP32 bulk; in FP64 its carried values push the
-// kernel, whose run descriptors are live as well, into register spills.
-template <typename R>
-constexpr bool lock_defer() { return sizeof(R) == 4; }
 constexpr int NT = 32 * CH;
 constexpr int LDS_DOUBLES =
     lagrange_lds_doubles<CH>() > remap_lds_doubles<double, CH>() ? lagrange_lds_doubles<CH>()
@@ -157,13 +152,14 @@ __global__ __launch_bounds__(NT, SALE_WAVES_POOL) void k_pool(const PoolRun<R> *
     if (ran) {
       const RunArgs<R> a = args_of(p);
       if (!remap) {
-        const bool t = lagrange_tile<R, CH, lock_defer<R>()>(a, tile, ctl->dt, lds);
+        const bool t = lagrange_tile<R, CH>(a, tile, ctl->dt, lds);
         if (t) atomicOr(&ctl->status, SALE_FLAG_TANGLE);
       } else {
         double amax;
-        bool bad;
-        remap_tile<R, CH>(a, tile, lds, &amax, &bad);
+        bool bad, tangle;
+        remap_tile<R, CH>(a, tile, lds, &amax, &bad, &tangle);
         block_max_to_ctl<NT>(ctl, amax, bad);
+        if (tangle) atomicOr(&ctl->status, SALE_FLAG_TANGLE);
       }
     }
     // finish the item: release its writes, count it; the last tile of the
@@ -217,7 +213,7 @@ __global__ __launch_bounds__(NT, waves_of_lock()) void k_lock_lagrange(const Poo
   Ctl *ctl = p.ctl;
   if (ctl->done) return;
   const RunArgs<R> a = args_of(p);
-  if (lagrange_tile<R, CH, lock_defer<R>()>(a, g - prefA[q], ctl->dt, lds)) atomicOr(&ctl->status, SALE_FLAG_TANGLE);
+  if (lagrange_tile<R, CH>(a, g - prefA[q], ctl->dt, lds)) atomicOr(&ctl->status, SALE_FLAG_TANGLE);
 }
 
 template <typename R>
@@ -232,9 +228,10 @@ __global__ __launch_bounds__(NT, waves_of_lock_remap<R>()) void k_lock_remap(con
   if (ctl->done) return;
   const RunArgs<R> a = args_of(p);
   double amax;
-  bool bad;
-  remap_tile<R, CH>(a, g - prefB[q], lds, &amax, &bad);
+  bool bad, tangle;
+  remap_tile<R, CH>(a, g - prefB[q], lds, &amax, &bad, &tangle);
   block_max_to_ctl<NT>(ctl, amax, bad);
+  if (tangle) atomicOr(&ctl->status, SALE_FLAG_TANGLE);
 }
 
 // device clock of each run's last completed step

@@ -13,8 +13,9 @@
 // masses, the dual fluxes, the kinetic-energy fix, walls, the next signal
 // speed -- is the first-order step's.
 //
-// Three passes, each a 32 x 16 tile of columns marched along z (every input
-// value read from memory once per tile, neighbours through LDS):
+// The Lagrangian densities first (one thread per cell), then three passes,
+// each a 32 x 16 tile of columns marched along z (every input value read
+// from memory once per tile, neighbours through LDS):
 //   k_cells2  fluxes through each cell's six faces, M, rho^{n+1}, e^pre
 //   k_nodes2  dual fluxes, reconstructed donor velocities, u^{n+1}, KE defect
 //   k_fix2    KE fix, e^{n+1}, the next signal speed (block max -> ctl)
@@ -50,6 +51,34 @@ __device__ __forceinline__ R donor_value(R q, R dq, R wgt, bool lower) {
   return lower ? q + dq * wgt : q - dq * wgt;
 }
 
+
+// ---- pass 0: Lagrangian densities -------------------------------------------------------
+// rho^L = m / V^L of every cell, V^L = V0 + the swept volumes of its six faces
+// (the Lagrange tile hands over each cell's three lower faces; an upper face
+// is the lower face of the +axis neighbour, zero on a wall). A cell with
+// V^L <= 0 is tangled: flag, and rho^L = 0.
+template <typename R>
+__global__ __launch_bounds__(256) void k_rho_lag(Mesh m, Ctl *ctl, State<R> cur, Geo<R> geo) {
+  if (ctl->done) return;
+  const int64_t c = blockIdx.x * (int64_t)256 + threadIdx.x;
+  if (c >= m.ncell) return;
+  const int i = (int)(c % m.nx);
+  const int64_t r = c / m.nx;
+  const int j = (int)(r % m.ny), k = (int)(r / m.ny);
+  const int64_t cpl = (int64_t)m.nx * m.ny;
+  const double vxu = i + 1 < m.nx ? (double)geo.dvx[c + 1] : 0.0;
+  const double vyu = j + 1 < m.ny ? (double)geo.dvy[c + m.nx] : 0.0;
+  const double vzu = k + 1 < m.nz ? (double)geo.dvz[c + cpl] : 0.0;
+  const double VL =
+      m.V0 + (((vxu - (double)geo.dvx[c]) + (vyu - (double)geo.dvy[c])) + (vzu - (double)geo.dvz[c]));
+  const R mc = cur.rho[c] * R(m.V0);
+  double rl = 0.0;
+  if (!(VL > 0.0))
+    atomicOr(&ctl->status, SALE_FLAG_TANGLE);
+  else
+    rl = (double)mc / VL;
+  geo.rl[c] = R(rl);
+}
 
 // ---- pass 1: face fluxes, cell masses, densities, pre-fix energies --------------------
 // A 32 x 16 tile of cell columns (halo 2 on each side: a face's donor
@@ -542,7 +571,7 @@ __global__ __launch_bounds__(FW * FH) void k_fix2(Mesh m, Ctl *ctl, State<R> cur
 
 template <typename R>
 hipError_t launch_remap2(const Mesh &m, Ctl *ctl, const Work<R> &w, int cur, hipStream_t s) {
-  if (m.order != 2 || !w.r2.M) return hipErrorInvalidValue;
+  if (m.order != 2 || !w.r2.M || !w.geo.rl) return hipErrorInvalidValue;
   const State<R> sc = w.s[cur], sn = w.s[1 - cur];
   // tiles of the three passes: about 6144 blocks, at least 8
   // planes per z segment
@@ -560,6 +589,7 @@ hipError_t launch_remap2(const Mesh &m, Ctl *ctl, const Work<R> &w, int cur, hip
   const Grid2 gnode = tiles(m.nx + 1, m.ny + 1, m.nz + 1, NTX, NTY);
   const Grid2 gf = tiles(m.nx, m.ny, m.nz, FTX, FTY);
   const Grid2 gcell = tiles(m.nx, m.ny, m.nz, CTX, CTY);
+  hipLaunchKernelGGL(k_rho_lag<R>, dim3((unsigned)((m.ncell + 255) / 256)), dim3(256), 0, s, m, ctl, sc, w.geo);
   hipLaunchKernelGGL(k_cells2<R>, dim3((unsigned)gcell.blocks()), dim3(CW2 * CH2), 0, s, m, ctl, sc, sn, w.geo, w.r2,
                      gcell);
   hipLaunchKernelGGL(k_nodes2<R>, dim3((unsigned)gnode.blocks()), dim3(NW * NH), 0, s, m, ctl, sc, sn, w.geo, w.up,

@@ -52,9 +52,10 @@ __global__ __launch_bounds__(32 * CH, (remap_waves<R, CH>())) void k_remap(RunAr
     return;
   }
   double amax;
-  bool bad;
-  remap_tile<R, CH>(a, b, lds, &amax, &bad);
+  bool bad, tangle;
+  remap_tile<R, CH>(a, b, lds, &amax, &bad, &tangle);
   block_max_to_ctl<32 * CH>(a.ctl, amax, bad);
+  if (tangle) atomicOr(&a.ctl->status, SALE_FLAG_TANGLE);
 }
 
 // ---------------------------------------------------------------------------------
@@ -394,11 +395,12 @@ template <typename R>
 size_t workspace_bytes(const Mesh &m) {
   const size_t cR = align256((size_t)m.ncell * sizeof(R)), nR = align256((size_t)m.nnode * sizeof(R));
   const size_t sD = align256((size_t)(m.ncell > m.nnode ? m.ncell : m.nnode) * sizeof(double));
-  // ctl | 2 states | u' | rho^L, e^L | 3 swept volumes | partials | scratch
-  const size_t r2 = m.order == 2 ? 5 * cR + nR : 0;  // second-order remap intermediates
+  // ctl | 2 states | u' | e^L | 3 swept volumes | partials | scratch
+  // (+ rho^L and the second-order remap's intermediates for order 2)
+  const size_t r2 = m.order == 2 ? 6 * cR + nR : 0;
   const size_t cD = align256((size_t)m.ncell * sizeof(double)), nD = align256((size_t)m.nnode * sizeof(double));
   const size_t lg = m.mode == 1 ? 6 * nD + 25 * cD : 0;  // positions x2, masses, corner forces
-  return align256(sizeof(Ctl)) + 2 * (2 * cR + 3 * nR) + 3 * nR + 2 * cR + 3 * cR +
+  return align256(sizeof(Ctl)) + 2 * (2 * cR + 3 * nR) + 3 * nR + cR + 3 * cR +
          align256(3 * TOT_BLOCKS * sizeof(double)) + sD + r2 + lg;
 }
 
@@ -429,7 +431,7 @@ void layout(const Mesh &m, void *ws, Ctl **ctl, Work<R> *w) {
   w->up = takeR(nR);
   w->vp = takeR(nR);
   w->wp = takeR(nR);
-  w->geo.rl = takeR(cR);
+  w->geo.rl = nullptr;
   w->geo.el = takeR(cR);
   w->geo.dvx = takeR(cR);
   w->geo.dvy = takeR(cR);
@@ -438,6 +440,7 @@ void layout(const Mesh &m, void *ws, Ctl **ctl, Work<R> *w) {
   w->scratch = takeD(sD);
   w->r2 = Rem2<R>{};
   if (m.order == 2) {
+    w->geo.rl = takeR(cR);
     for (int a = 0; a < 3; a++) w->r2.mu[a] = takeR(cR);
     w->r2.M = takeR(cR);
     w->r2.epre = takeR(cR);

@@ -128,7 +128,7 @@ __device__ __forceinline__ void tile_of(const Grid2 &g, int b, int &tx, int &ty,
 // LDS doubles needed by each tile function for a 32 x CH tile
 template <int CH>
 constexpr int lagrange_lds_doubles() {
-  return 13 * 32 * CH;
+  return 11 * 32 * CH;
 }
 // (remap: two double planes, then 16 planes of the bulk type R)
 template <typename R, int CH>
@@ -148,17 +148,12 @@ constexpr int remap_lds_doubles() {
 //       half is formed once and carried one plane
 //   P3  u' and delta = dt (u + u')/2 of node plane k: gather of P* over the
 //       node's 8 cells as a per-plane sum carried one plane            (LDS)
-//   P4  swept volumes of the faces of cell plane k-1 (they need delta on node
-//       planes k-1 and k only) and its compatible-energy work
-//   P5  V^L, rho^L, e^L of cell plane k-1; hand-off to remap_tile. It needs
-//       the neighbours' x/y swept volumes: with DEFER it runs after the next
-//       iteration's P1 barrier (they stay in LDS until that iteration's P4),
-//       three barriers per plane instead of four; without, after a barrier
-//       of its own. The values it carries cost registers, which the
-//       multi-run kernels (run descriptors live too) do not have to spare.
-//       Both forms do the same arithmetic.
-// Returns true if a tangled cell was seen.
-template <typename R, int CH, bool DEFER = true>
+//   P4  swept volumes of the three lower faces of cell plane k-1 (they need
+//       delta on node planes k-1 and k only), its compatible-energy work and
+//       e^L; hand-off to remap_tile, which forms V^L and rho^L from the six
+//       faces' swept volumes
+// Returns true if a tangled cell was seen (the predictor's volume).
+template <typename R, int CH>
 __device__ bool lagrange_tile(const RunArgs<R> &a, int b, double dtd, double *lds) {
   constexpr int CW = 32, NTH = CW * CH, TX = CW - 3, TY = CH - 3;
   const Mesh &m = a.m;
@@ -180,13 +175,11 @@ __device__ bool lagrange_tile(const RunArgs<R> &a, int b, double dtd, double *ld
   const int64_t cpl = (int64_t)m.nx * m.ny, npl = (int64_t)(m.nx + 1) * (m.ny + 1);
   const uint32_t cix = ccol ? (uint32_t)(gi + m.nx * gj) : 0u, nix = ncol ? (uint32_t)(gi + (m.nx + 1) * gj) : 0u;
 
-  // LDS: bulk planes as R, delta ring and swept volumes as double
+  // LDS: bulk planes as R, delta ring as double
   R(*sU)[CH][CW] = reinterpret_cast<R(*)[CH][CW]>(lds);                // [3]
   R(*sP)[CW] = reinterpret_cast<R(*)[CW]>(lds + 3 * CH * CW);          // P*
   R(*sM)[CW] = reinterpret_cast<R(*)[CW]>(lds + 4 * CH * CW);          // m
   double(*sD)[3][CH][CW] = reinterpret_cast<double(*)[3][CH][CW]>(lds + 5 * CH * CW);  // [2][3]
-  double(*sVX)[CW] = reinterpret_cast<double(*)[CW]>(lds + 11 * CH * CW);
-  double(*sVY)[CW] = reinterpret_cast<double(*)[CW]>(lds + 12 * CH * CW);
 
   for (int q = threadIdx.x; q < 2 * 3 * CH * CW; q += NTH) (&sD[0][0][0][0])[q] = 0.0;
 
@@ -219,28 +212,6 @@ __device__ bool lagrange_tile(const RunArgs<R> &a, int b, double dtd, double *ld
   fetch(Z0 - 2);
   settle(fu), settle(fv), settle(fw), settle(frho), settle(fe);
 
-  // ---- P5: V^L, rho^L, e^L of cell plane cp, from the x/y swept volumes P4
-  // left in LDS, the cell's z-face swept volumes (lower: h_vz, upper: still
-  // in dvz_lo) and its e^L and mass held in registers
-  double h_el = 0.0, h_vz = 0.0;
-  R h_m = 0;
-  auto finish = [&](int cp) {
-    if (own_cell && cp >= Z0 && cp < Z1) {
-      const double VL = m.V0 + (((sVX[cj][ci + 1] - sVX[cj][ci]) + (sVY[cj + 1][ci] - sVY[cj][ci])) + (dvz_lo - h_vz));
-      double rl = 0.0;
-      if (!(VL > 0.0))
-        tangle = true;
-      else
-        rl = (double)h_m / VL;
-      const uint32_t oR = cix * (uint32_t)sizeof(R);
-      plane_at<R>(a.geo.rl, cpl, cp, oR) = R(rl);
-      plane_at<R>(a.geo.el, cpl, cp, oR) = R(h_el);
-      plane_at<R>(a.geo.dvx, cpl, cp, oR) = R(sVX[cj][ci]);
-      plane_at<R>(a.geo.dvy, cpl, cp, oR) = R(sVY[cj][ci]);
-      plane_at<R>(a.geo.dvz, cpl, cp, oR) = R(h_vz);
-    }
-  };
-
   for (int k = Z0 - 2; k <= Z1; k++) {
     // ---- P1 ----
     const R un = fu, vn = fv, wn = fw, rho_k = frho, e_k = fe;
@@ -249,8 +220,6 @@ __device__ bool lagrange_tile(const RunArgs<R> &a, int b, double dtd, double *ld
     sU[1][cj][ci] = vn;
     sU[2][cj][ci] = wn;
     __syncthreads();
-    // ---- P5 of cell plane k-2 (its swept volumes are in LDS until P4) ----
-    if constexpr (DEFER) finish(k - 2);
     // ---- P2 ----
     R ps = 0, mc = 0, imc = 0;
     {
@@ -316,10 +285,9 @@ __device__ bool lagrange_tile(const RunArgs<R> &a, int b, double dtd, double *ld
       w0 = wn;
     }
     __syncthreads();
-    // ---- P4: faces and work of cell plane k-1 ----
+    // ---- P4: faces, work and e^L of cell plane k-1 ----
     const int cp = k - 1;
     const bool plane_ok = cp >= 0 && cp < m.nz && k > Z0 - 2;
-    double work = 0.0, dvz_up = 0.0;
     {
       const double(*A)[CH][CW] = sD[cp & 1];  // node plane k-1
       const double(*B)[CH][CW] = sD[k & 1];   // node plane k
@@ -330,74 +298,50 @@ __device__ bool lagrange_tile(const RunArgs<R> &a, int b, double dtd, double *ld
         qzd = ((B[2][cj][ci] + B[2][cj][ci + 1]) + B[2][cj + 1][ci]) + B[2][cj + 1][ci + 1];
       }
       // work = sum_p S_cp . delta_p (= dt sum S.u_bar) of cell plane k-1
-      work = (m.ax * (pxd + qxd) + m.ay * (pyd + qyd)) + m.az * (qzd - pzd);
+      const double work = (m.ax * (pxd + qxd) + m.ay * (pyd + qyd)) + m.az * (qzd - pzd);
       pxd = qxd;
       pyd = qyd;
       pzd = qzd;
-      double vx = 0.0, vy = 0.0;
-      // x face at node column gi between cells gi-1, gi; corners (s: y, t: z)
-      if (plane_ok && ci >= 1 && ci <= TX + 1 && cj >= 1 && cj <= TY && gi >= 1 && gi <= m.nx - 1 && gj >= 0 &&
-          gj < m.ny) {
+      const bool mine = own_cell && cp >= Z0 && cp < Z1;
+      double vx = 0.0, vy = 0.0, dvz_up = 0.0;
+      // lower x face (node column gi, between cells gi-1 and gi); corners (s: y, t: z)
+      if (mine && plane_ok && gi >= 1) {
         const double d0[3] = {A[0][cj][ci], A[1][cj][ci], A[2][cj][ci]};
         const double d1[3] = {A[0][cj + 1][ci], A[1][cj + 1][ci], A[2][cj + 1][ci]};
         const double d2[3] = {B[0][cj][ci], B[1][cj][ci], B[2][cj][ci]};
         const double d3[3] = {B[0][cj + 1][ci], B[1][cj + 1][ci], B[2][cj + 1][ci]};
-        vx = swept_volume(d0, d1, d2, d3, m.hyz, m.hdy, m.hdz);
+        vx = swept_volume(d0, d1, d2, d3, m.ax, m.edy, m.edz);
       }
-      // y face at node row gj between cells gj-1, gj; corners (s: z, t: x); comps (y, z, x)
-      if (plane_ok && ci >= 1 && ci <= TX && cj >= 1 && cj <= TY + 1 && gj >= 1 && gj <= m.ny - 1 && gi >= 0 &&
-          gi < m.nx) {
+      // lower y face (node row gj, between cells gj-1 and gj); corners (s: z, t: x); comps (y, z, x)
+      if (mine && plane_ok && gj >= 1) {
         const double d0[3] = {A[1][cj][ci], A[2][cj][ci], A[0][cj][ci]};
         const double d1[3] = {B[1][cj][ci], B[2][cj][ci], B[0][cj][ci]};
         const double d2[3] = {A[1][cj][ci + 1], A[2][cj][ci + 1], A[0][cj][ci + 1]};
         const double d3[3] = {B[1][cj][ci + 1], B[2][cj][ci + 1], B[0][cj][ci + 1]};
-        vy = swept_volume(d0, d1, d2, d3, m.hzx, m.hdz, m.hdx);
+        vy = swept_volume(d0, d1, d2, d3, m.ay, m.edz, m.edx);
       }
-      // z face at node plane k between cells k-1, k; corners (s: x, t: y); comps (z, x, y)
+      // z face at node plane k between cells k-1 and k (the lower z face of
+      // cell plane k); corners (s: x, t: y); comps (z, x, y)
       if (own_cell && k >= 1 && k <= m.nz - 1) {
         const double d0[3] = {B[2][cj][ci], B[0][cj][ci], B[1][cj][ci]};
         const double d1[3] = {B[2][cj][ci + 1], B[0][cj][ci + 1], B[1][cj][ci + 1]};
         const double d2[3] = {B[2][cj + 1][ci], B[0][cj + 1][ci], B[1][cj + 1][ci]};
         const double d3[3] = {B[2][cj + 1][ci + 1], B[0][cj + 1][ci + 1], B[1][cj + 1][ci + 1]};
-        dvz_up = swept_volume(d0, d1, d2, d3, m.hxy, m.hdx, m.hdy);
+        dvz_up = swept_volume(d0, d1, d2, d3, m.az, m.edx, m.edy);
       }
-      sVX[cj][ci] = vx;
-      sVY[cj][ci] = vy;
-    }
-    if constexpr (DEFER) {  // P5 of this plane after the next plane's first barrier
-      if (own_cell && cp >= Z0 && cp < Z1) {
-        h_el = (double)e1 - (double)ps1 * work / (double)m1;
-        h_vz = dvz_lo;
-        h_m = m1;
-      }
-    } else {  // P5 of this plane now (the same arithmetic as finish())
-      __syncthreads();
       settle(fu), settle(fv), settle(fw), settle(frho), settle(fe);  // loads issued in P1
-      if (own_cell && cp >= Z0 && cp < Z1) {
-        const double VL =
-            m.V0 + (((sVX[cj][ci + 1] - sVX[cj][ci]) + (sVY[cj + 1][ci] - sVY[cj][ci])) + (dvz_up - dvz_lo));
-        double rl = 0.0;
-        if (!(VL > 0.0))
-          tangle = true;
-        else
-          rl = (double)m1 / VL;
+      if (mine) {
         const uint32_t oR = cix * (uint32_t)sizeof(R);
-        plane_at<R>(a.geo.rl, cpl, cp, oR) = R(rl);
         plane_at<R>(a.geo.el, cpl, cp, oR) = R((double)e1 - (double)ps1 * work / (double)m1);
-        plane_at<R>(a.geo.dvx, cpl, cp, oR) = R(sVX[cj][ci]);
-        plane_at<R>(a.geo.dvy, cpl, cp, oR) = R(sVY[cj][ci]);
+        plane_at<R>(a.geo.dvx, cpl, cp, oR) = R(vx);
+        plane_at<R>(a.geo.dvy, cpl, cp, oR) = R(vy);
         plane_at<R>(a.geo.dvz, cpl, cp, oR) = R(dvz_lo);
       }
+      dvz_lo = dvz_up;
     }
-    dvz_lo = dvz_up;
     ps1 = ps;
     e1 = e_k;
     m1 = mc;
-    if constexpr (DEFER) settle(fu), settle(fv), settle(fw), settle(frho), settle(fe);  // loads issued in P1
-  }
-  if constexpr (DEFER) {
-    __syncthreads();
-    finish(Z1 - 1);
   }
   return tangle;
 }
@@ -423,7 +367,8 @@ __device__ bool lagrange_tile(const RunArgs<R> &a, int b, double dtd, double *ld
 // Writes the new state; returns the tile's largest signal speed in *amax and
 // whether an owned cell or node was inadmissible in *bad.
 template <typename R, int CH>
-__device__ void remap_tile(const RunArgs<R> &a, int b, double *lds, double *amax_out, bool *bad_out) {
+__device__ void remap_tile(const RunArgs<R> &a, int b, double *lds, double *amax_out, bool *bad_out,
+                           bool *tangle_out) {
   constexpr int CW = 32, NTH = CW * CH, TX = CW - 4, TY = CH - 4;
   const Mesh &m = a.m;
   int tx, ty, seg;
@@ -480,18 +425,23 @@ __device__ void remap_tile(const RunArgs<R> &a, int b, double *lds, double *amax
   bool bad = false;
 
   // global loads run one plane ahead
-  R f_rl = 0, f_el = 0, f_rho = 0, f_u = 0, f_v = 0, f_w = 0;
-  double f_vx = 0, f_vy = 0, f_vz = 0;
+  // (cell plane cp: e^L, rho, the swept volumes of the cell's lower x and y
+  // faces and of its upper x, y and z faces -- the lower faces of its +x,
+  // +y and +z neighbours, zero on a wall)
+  R f_el = 0, f_rho = 0, f_u = 0, f_v = 0, f_w = 0;
+  R f_vx = 0, f_vy = 0, f_vxu = 0, f_vyu = 0, f_vzu = 0;
+  const bool xup = ccol && gi + 1 < m.nx, yup = ccol && gj + 1 < m.ny;
   auto fetch = [&](int cp) {
-    f_rl = f_el = f_rho = f_u = f_v = f_w = R(0);
-    f_vx = f_vy = f_vz = 0.0;
+    f_el = f_rho = f_u = f_v = f_w = R(0);
+    f_vx = f_vy = f_vxu = f_vyu = f_vzu = R(0);
     if (ccol && cp >= 0 && cp < m.nz) {
       const uint32_t oR = cix * (uint32_t)sizeof(R);
-      f_rl = plane_at<const R>(a.geo.rl, cpl, cp, oR);
       f_el = plane_at<const R>(a.geo.el, cpl, cp, oR);
-      f_vx = (double)plane_at<const R>(a.geo.dvx, cpl, cp, oR);
-      f_vy = (double)plane_at<const R>(a.geo.dvy, cpl, cp, oR);
-      f_vz = (double)plane_at<const R>(a.geo.dvz, cpl, cp, oR);
+      f_vx = plane_at<const R>(a.geo.dvx, cpl, cp, oR);
+      f_vy = plane_at<const R>(a.geo.dvy, cpl, cp, oR);
+      if (xup) f_vxu = plane_at<const R>(a.geo.dvx, cpl, cp, oR + (uint32_t)sizeof(R));
+      if (yup) f_vyu = plane_at<const R>(a.geo.dvy, cpl, cp, oR + (uint32_t)(m.nx * sizeof(R)));
+      if (cp + 1 < m.nz) f_vzu = plane_at<const R>(a.geo.dvz, cpl, cp + 1, oR);
       f_rho = plane_at<const R>(a.cur.rho, cpl, cp, oR);
     }
     if (ncol && cp >= 0 && cp <= m.nz) {
@@ -504,20 +454,40 @@ __device__ void remap_tile(const RunArgs<R> &a, int b, double *lds, double *amax
   // the u' ring starts empty (node planes below Z0-2 only feed non-owned results)
   for (int q = threadIdx.x; q < 3 * 3 * CH * CW; q += NTH) (&UPR[0][0][0][0])[q] = R(0);
   fetch(Z0 - 2);
-  settle(f_rl), settle(f_el), settle(f_rho), settle(f_u), settle(f_v), settle(f_w);
-  settle(f_vx), settle(f_vy), settle(f_vz);
+  // swept volume of the lower z face of cell plane c+1 (carried: the upper
+  // face loaded with plane c)
+  R dvz_n = 0;
+  if (ccol && Z0 - 2 >= 1 && Z0 - 2 < m.nz) dvz_n = plane_at<const R>(a.geo.dvz, cpl, Z0 - 2, cix * (uint32_t)sizeof(R));
+  settle(f_el), settle(f_rho), settle(f_u), settle(f_v), settle(f_w);
+  settle(f_vx), settle(f_vy), settle(f_vxu), settle(f_vyu), settle(f_vzu), settle(dvz_n);
+  bool tangle = false;
   __syncthreads();
 
   for (int c = Z0 - 3; c <= Z1; c++) {  // c >= -3
     const int c1 = c + 1;
     const int rA = (c + 5) % 3, rB = (c + 6) % 3, rC = (c + 7) % 3;  // ring rows of c-1, c, c+1
     // ---- P1 --------------------------------------------------------------------------
-    const R rl_n = f_rl, el_n = f_el, rho_n = f_rho;
-    const double dvz_n = f_vz;
+    const R el_n = f_el, rho_n = f_rho;
+    // V^L and rho^L of cell plane c+1 from the swept volumes of its six faces
+    R rl_n = 0;
+    {
+      const R mc = rho_n * V0;
+      const double VL = m.V0 + ((((double)f_vxu - (double)f_vx) + ((double)f_vyu - (double)f_vy)) +
+                                ((double)f_vzu - (double)dvz_n));
+      if (ccol && c1 >= 0 && c1 < m.nz) {
+        if (!(VL > 0.0)) {
+          if (own_cell && c1 >= Z0 && c1 < Z1) tangle = true;
+        } else {
+          rl_n = R((double)mc / VL);
+        }
+      }
+    }
+    const double dvz_f = (double)dvz_n;  // z face between cell planes c and c+1
+    dvz_n = f_vzu;
     RS(RL)[cj][ci] = rl_n;
     RS(EL)[cj][ci] = el_n;
-    sVX[cj][ci] = f_vx;
-    sVY[cj][ci] = f_vy;
+    sVX[cj][ci] = (double)f_vx;
+    sVY[cj][ci] = (double)f_vy;
     UPR[rC][0][cj][ci] = f_u;  // node plane c+1 (slot last read as plane c-2)
     UPR[rC][1][cj][ci] = f_v;
     UPR[rC][2][cj][ci] = f_w;
@@ -553,8 +523,8 @@ __device__ void remap_tile(const RunArgs<R> &a, int b, double *lds, double *amax
       };
       R muz_n = 0, epz_n = 0;
       if (ccol && c1 >= 1 && c1 <= m.nz - 1) {  // z face between cells c and c+1
-        const bool lower = dvz_n > 0.0;
-        muz_n = (lower ? rl_c : rl_n) * R(dvz_n);
+        const bool lower = dvz_f > 0.0;
+        muz_n = (lower ? rl_c : rl_n) * R(dvz_f);
         epz_n = muz_n * (lower ? el_c : el_n);
       }
       R nm = 0, ne = 0, sx = 0, sy = 0, M = 0, mo = 0, sz = 0;
@@ -627,8 +597,8 @@ __device__ void remap_tile(const RunArgs<R> &a, int b, double *lds, double *amax
       pr_c1 = pr;
     }
     __syncthreads();
-    settle(f_rl), settle(f_el), settle(f_rho), settle(f_u), settle(f_v), settle(f_w);  // loads issued in P1
-    settle(f_vx), settle(f_vy), settle(f_vz);
+    settle(f_el), settle(f_rho), settle(f_u), settle(f_v), settle(f_w);  // loads issued in P1
+    settle(f_vx), settle(f_vy), settle(f_vxu), settle(f_vyu), settle(f_vzu);
     // ---- P5: node plane c --------------------------------------------------------------
     {
       R un = 0, vn = 0, wn = 0, sp = 0, dk = 0;
@@ -742,6 +712,7 @@ __device__ void remap_tile(const RunArgs<R> &a, int b, double *lds, double *amax
   __syncthreads();  // the last plane's P6 reads are done before the LDS is reused
   *amax_out = amax;
   *bad_out = bad;
+  *tangle_out = tangle;
 }
 
 // No-op step of a tile: carry the owned part of the state into the other buffer.
