@@ -1,0 +1,178 @@
+"""Full-size parity in the benchmark's launch configuration.
+
+The 320^3 mesh in the benchmark's launch shape (tiles of 32 x 16 columns,
+about 3072 blocks per kernel, z segments of about 33 planes) is checked with
+data in every tile and every z segment: one step from a random state (values
+independent per cell and node, so every tile seam, segment seam, donor
+direction and viscosity branch sees real data) against one oracle step from
+the same state, in FP64, MIXED32 and the second-order remap; one step from
+the Sedov blast grown across several tiles and segments (t = 0.035, shock
+radius about 0.27, 72 cells); and the whole Sedov 64^3 trajectory to t = 1
+against the oracle's, compared every 50 steps.
+
+Besides the max-normalised metric (FP64 bar 1e-12 per field per step), each
+check reports errors measured cell by cell: |g - o| / max(|o|, floor) and
+the L1-relative error over the cells the step changed (tests/parity.py).
+Their FP64 bars: per-cell relative 1e-11, L1 over changed cells 1e-13 for a
+single step. A cell's update adds the fluxes of its faces to its own mass
+and energy; where a cold cell takes the flux of a hot neighbour the
+rounding of terms much larger than the cell's own value lands in it, so the
+per-cell error is the rounding unit (1.1e-16) times that ratio, which for
+the blast's front stays below 1e5.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as orc
+from oracle.exact import sedov_radius
+from paper_2209_01983_amd import sale
+from paper_2209_01983_amd.inputs import random_state
+
+from parity import TOL64, assert_parity, errors, grid_of, local_errors, oracle_state, say  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+N = 320
+LOCAL64 = 1e-11    # per-cell relative, FP64, one step
+L1_64 = 1e-13      # L1-relative over the changed cells, FP64, one step
+TOL32_STEP = 5e-6  # MIXED32 single-step bar (max-normalised), as for the other MIXED32 tests
+L1_32 = 5e-7       # MIXED32 L1-relative over the changed cells, one step
+
+
+def user_run(cfg, st):
+    p, keep = sale.user_problem(st["rho"], st["e"], st["u"], st["v"], st["w"])
+    return sale.SaleRun(cfg, p, keepalive=keep)
+
+
+def bench_shape(r):
+    r.set_launch(16, 16, 3072)
+
+
+def one_step(r, cfg, what, prev_state=None):
+    """One oracle step from the run's current state against one GPU step."""
+    t, steps, _, _ = r.state()
+    s = oracle_state(r.fields(), t=t, step=steps)
+    prev = s.copy() if hasattr(s, "copy") else None
+    o = orc.Oracle(grid_of(cfg))
+    assert o.step(s)[0] == orc.OK, what
+    o.close()
+    r.step()
+    g = r.fields()
+    return g, s, prev
+
+
+def test_fp64_320_random_state_every_tile_and_segment():
+    cfg = sale.make_config(N, N, N, hi=(1.2, 1.2, 1.2), t_end=100.0)
+    say("fp64 320^3 random state")
+    st = random_state(N, N, N, seed=320)
+    r = user_run(cfg, st)
+    bench_shape(r)
+    g, s, prev = one_step(r, cfg, "fp64 320 random")
+    err = assert_parity(g, s, what="fp64 320^3 random")
+    loc = local_errors(g, s, prev)
+    say("fp64 320^3 random: max-normalised", err, "local", loc)
+    assert max(loc["local"].values()) <= LOCAL64, loc
+    assert max(loc["l1"].values()) <= L1_64, loc
+    r.close()
+
+
+def test_mixed32_320_random_smooth_state_every_tile_and_segment():
+    cfg = sale.make_config(N, N, N, hi=(1.2, 1.2, 1.2), t_end=100.0, precision=sale.SALE_MIXED32)
+    say("mixed32 320^3 random smooth state")
+    st = random_state(N, N, N, seed=321, smooth=True)
+    r = user_run(cfg, st)
+    bench_shape(r)
+    g, s, prev = one_step(r, cfg, "mixed32 320 random")
+    err = errors(g, s)
+    loc = local_errors(g, s, prev)
+    say("mixed32 320^3 random smooth: max-normalised", err, "local", loc)
+    assert max(err.values()) <= TOL32_STEP, err
+    assert max(loc["l1"].values()) <= L1_32, loc
+    r.close()
+
+
+def test_order2_320_random_state_every_tile_and_segment():
+    cfg = sale.make_config(N, N, N, hi=(1.2, 1.2, 1.2), t_end=100.0, remap_order=2)
+    say("order-2 320^3 random state")
+    st = random_state(N, N, N, seed=322)
+    r = user_run(cfg, st)
+    bench_shape(r)
+    g, s, prev = one_step(r, cfg, "order2 320 random")
+    err = assert_parity(g, s, what="order-2 320^3 random")
+    loc = local_errors(g, s, prev)
+    say("order-2 320^3 random: max-normalised", err, "local", loc)
+    assert max(loc["local"].values()) <= LOCAL64, loc
+    assert max(loc["l1"].values()) <= L1_64, loc
+    r.close()
+
+
+T_GROWN = 0.035  # Sedov shock radius 1.0328 t^0.4 = 0.27: 72 cells at 320^3
+
+
+@pytest.mark.parametrize("precision", [sale.SALE_FP64, sale.SALE_MIXED32])
+def test_sedov_320_grown_blast_single_step(precision):
+    """The Sedov blast of the benchmark's workload grown across two z
+    segments and the first tiles in x and y, then one step against the
+    oracle's step from the same state."""
+    name = "fp64" if precision == sale.SALE_FP64 else "mixed32"
+    cfg = sale.make_config(N, N, N, hi=(1.2, 1.2, 1.2), t_end=1.0, precision=precision)
+    say(f"sedov 320^3 {name}: run to t = {T_GROWN}")
+    r = sale.SaleRun(cfg, sale.sedov_problem())
+    bench_shape(r)
+    assert r.run(t_end=T_GROWN) == sale.SALE_DONE
+    assert r.run(t_end=1.0, max_steps=0) == sale.SALE_OK
+    t, steps, _, flags = r.state()
+    assert t == T_GROWN and flags == 0
+    rho = r.fields(("rho",))["rho"]
+    rr = (np.arange(N) + 0.5) * 1.2 / N
+    radius = rr[np.argmax(rho[0, 0, :])]
+    say(f"sedov 320^3 {name}: {steps} steps, shock at {radius:.3f} ({radius / 1.2 * N:.0f} cells), "
+        f"exact {sedov_radius(T_GROWN):.3f}")
+    assert radius / 1.2 * N > 66  # past two z segments and two tiles in x and y
+    g, s, prev = one_step(r, cfg, f"sedov 320 {name}")
+    err = errors(g, s)
+    loc = local_errors(g, s, prev, floor={"e": 2.5e-6, "rho": 1.0})
+    say(f"sedov 320^3 {name} grown: max-normalised", err, "local", loc)
+    if precision == sale.SALE_FP64:
+        assert max(err.values()) <= TOL64, err
+        assert max(loc["local"].values()) <= LOCAL64, loc
+        assert max(loc["l1"].values()) <= L1_64, loc
+    else:
+        assert max(err.values()) <= TOL32_STEP, err
+        assert max(loc["l1"].values()) <= L1_32, loc
+    r.close()
+
+
+def test_sedov_64_whole_trajectory_to_t1():
+    """The whole Sedov 64^3 run to t = 1 against the oracle's run, compared
+    every 50 steps and at the end. Rounding differences (FMA contraction,
+    reciprocals) start at 1e-16 and grow along the trajectory; the bar on
+    the whole run is 1e-10 per field (max-normalised), the per-step bar of
+    1e-12 holds at every point of it (single steps from the GPU's state are
+    checked in the 128^3 test)."""
+    n = 64
+    cfg = sale.make_config(n, n, n, hi=(1.2, 1.2, 1.2), t_end=1.0)
+    g = grid_of(cfg)
+    s = orc.sedov(g)
+    o = orc.Oracle(g)
+    r = sale.SaleRun(cfg, sale.sedov_problem())
+    worst, k, growth = 0.0, 0, []
+    while True:
+        rc, _ = o.step(s)
+        if rc == orc.DONE:
+            break
+        assert rc == orc.OK
+        r.step()
+        k += 1
+        if k % 50 == 0:
+            err = errors(r.fields(), s)
+            worst = max(worst, max(err.values()))
+            growth.append((k, max(err.values())))
+            assert max(err.values()) <= 1e-10, (k, err)
+    t, steps, _, flags = r.state()
+    assert r.run() == sale.SALE_DONE
+    assert steps == s.step and flags == 0 and r.state()[0] == 1.0
+    err = errors(r.fields(), s)
+    loc = local_errors(r.fields(), s, orc.sedov(g), floor={"e": 2.5e-6, "rho": 1.0})
+    say(f"sedov 64^3 to t = 1: {steps} steps; error every 500 steps", growth[9::10], "final", err, "local", loc)
+    assert max(err.values()) <= 1e-10, err
