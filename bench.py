@@ -62,15 +62,17 @@ def parse():
     ap.add_argument("--n", type=int, default=320, help="cells per axis of the headline workload")
     ap.add_argument("--quick", action="store_true", help="headline and roofline only")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-steps", type=int, default=10)
+    ap.add_argument("--cpu-steps", type=int, default=20, help="oracle steps on all threads")
+    ap.add_argument("--cpu-steps-one", type=int, default=5, help="oracle steps on one thread")
     ap.add_argument("--serve-requests", type=int, default=1000)
     ap.add_argument("--serve-budget-gb", type=float, default=64.0)
     ap.add_argument("--no-tune", action="store_true", help="default launch shape, no autotuning")
     ap.add_argument("--shape", default="", metavar="A,B,T",
                     help="launch shape of the headline runs (tile rows of the two step kernels, z-split "
                          "target); skips the autotuner")
-    ap.add_argument("--precision-report", type=int, default=0, metavar="N",
-                    help="also run the N^3 Sedov to t = 1 in FP64 and MIXED32 and report per-field errors")
+    ap.add_argument("--precision-report", type=int, default=None, metavar="N",
+                    help="run the N^3 Sedov to t = 1 in FP64 and MIXED32 and report per-field errors "
+                         "(default: 128 in the full run, none with --quick; 0: none)")
     ap.add_argument("--section", default="", choices=("", "latency", "sedov128", "noh128", "lagrange128", "batched", "serving"),
                     help="run only this extra block and print its JSON (for profiling it)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -263,25 +265,49 @@ def lagrange128(steps=100, warmup=10):
             "sim_time_end_of_window": t}
 
 
+def _with_pool_mode(persistent, fn):
+    """Run fn() with pools created in the persistent-kernel advance mode (the
+    library reads SALE_POOL_PERSISTENT when a pool is created) or in the
+    default lockstep mode."""
+    old = os.environ.get("SALE_POOL_PERSISTENT")
+    os.environ["SALE_POOL_PERSISTENT"] = "1" if persistent else "0"
+    try:
+        return fn()
+    finally:
+        if old is None:
+            del os.environ["SALE_POOL_PERSISTENT"]
+        else:
+            os.environ["SALE_POOL_PERSISTENT"] = old
+
+
 def batched(seq_fp64=True):
     from paper_2209_01983_amd import sale, workloads
     from paper_2209_01983_amd.inputs import BATCH_SEED, batch_mix
 
     reqs = batch_mix(256, seed=BATCH_SEED)
     steps = 200
-    # one untimed warm-up launch on a small batch (code objects, clocks)
-    workloads.run_batched(reqs[:8], 5, sale.SALE_MIXED32)
-    r32 = workloads.run_batched(reqs, steps, sale.SALE_MIXED32)
-    r32["pool"].close()
-    out = {"workload": "256 runs, edges 16..64 (seed 2209), 128 sod + 128 sedov, 200 steps, "
-                       "one pool advance (lockstep launches over all runs)",
+    out = {"workload": "256 runs, edges 16..64 (seed 2209), 128 sod + 128 sedov, 200 steps, one pool advance",
            "cells_total": sum(workloads.cells(r) for r in reqs),
-           "mixed32": {"cell_updates_per_s": r32["cell_updates_per_s"], "makespan_s": r32["makespan_s"],
-                       "latency_p50_s": pct(r32["latency_s"], 50), "latency_p99_s": pct(r32["latency_s"], 99)}}
-    r64 = workloads.run_batched(reqs, steps, sale.SALE_FP64)
-    r64["pool"].close()
-    out["fp64"] = {"cell_updates_per_s": r64["cell_updates_per_s"], "makespan_s": r64["makespan_s"],
-                   "latency_p50_s": pct(r64["latency_s"], 50), "latency_p99_s": pct(r64["latency_s"], 99)}
+           "modes": {"persistent": "one launch of the persistent kernel per advance (work items pulled from a "
+                                   "device queue, per-run phase waits)",
+                     "lockstep": "per step: one launch each for dt, the Lagrange tiles of all runs and the remap "
+                                 "tiles of all runs"}}
+    for mode, persistent in (("persistent", True), ("lockstep", False)):
+        def one(prec):
+            r = workloads.run_batched(reqs, steps, prec)
+            r["pool"].close()
+            return {"cell_updates_per_s": r["cell_updates_per_s"], "makespan_s": r["makespan_s"],
+                    "latency_p50_s": pct(r["latency_s"], 50), "latency_p99_s": pct(r["latency_s"], 99)}
+
+        def both():
+            # one untimed warm-up advance on a small batch (code objects, clocks)
+            workloads.run_batched(reqs[:8], 5, sale.SALE_MIXED32)["pool"].close()
+            return {"mixed32": one(sale.SALE_MIXED32), "fp64": one(sale.SALE_FP64)}
+
+        say("batched", mode)
+        out[mode] = _with_pool_mode(persistent, both)
+    # the headline figures of the block: the persistent launch
+    out["mixed32"], out["fp64"] = out["persistent"]["mixed32"], out["persistent"]["fp64"]
     if seq_fp64:
         wall, cps, lat = workloads.run_sequential(reqs, steps, sale.SALE_FP64)
         out["fp64_sequential_plain"] = {"cell_updates_per_s": cps, "wall_s": wall,
@@ -353,32 +379,101 @@ def precision_report(n):
         r.close()
     a, b = fields["mixed32"], fields["fp64"]
     vs = max(np.abs(b[k]).max() for k in ("u", "v", "w"))
+    spd = np.sqrt(b["u"] ** 2 + b["v"] ** 2 + b["w"] ** 2)
+    # cell by cell: |a - b| / max(|b|, floor), floors the background density
+    # and energy of the Sedov set-up and 1e-3 of the largest speed component
+    floors = {"rho": 1.0, "e": 1e-6 / (0.4 * 1.0), "u": 1e-3 * vs}
     err = {}
     for k in ("rho", "e", "u", "v", "w"):
         d = np.abs(a[k] - b[k])
         scale = vs if k in ("u", "v", "w") else np.abs(b[k]).max()
+        ref = np.maximum(spd, floors["u"]) if k in ("u", "v", "w") else np.maximum(np.abs(b[k]), floors[k])
+        r = d / ref
         err[k] = {"l1_rel": float(d.sum() / max(np.abs(b[k]).sum(), 1e-300)),
-                  "linf_rel": float(d.max() / max(scale, 1e-300))}
+                  "linf_rel": float(d.max() / max(scale, 1e-300)),
+                  "cell_rel_quantiles": {q: float(np.quantile(r, p))
+                                         for q, p in (("p50", 0.5), ("p99", 0.99), ("p999", 0.999), ("max", 1.0))}}
     out["mixed32_vs_fp64"] = err
+    out["note"] = ("MIXED32 against the FP64 path (which matches the FP64 oracle to 1e-12 per field per step); "
+                   "linf_rel against each field's largest value (velocity: the largest speed component); "
+                   "cell_rel against max(|fp64|, floor): background rho 1, background e 2.5e-6, "
+                   "1e-3 of the largest speed component")
     return out
 
 
-def cpu_bench(n, steps):
-    """The FP64 oracle on this host (all cores, OpenMP): one warm-up step,
-    then `steps` timed steps of the same Sedov workload."""
+def host_cpu():
+    """Model name and CPU counts of this host."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        affinity = None
+    return {"model": model, "logical_cpus": os.cpu_count(), "cpus_in_affinity": affinity}
+
+
+def cpu_sedov_leg(o, s, n, steps, threads=None):
+    """`steps` FP64 oracle steps of the Sedov n^3 workload on `threads`
+    OpenMP threads (None: the process default): (cell-updates/s, threads, s)."""
     from oracle import oracle as orc
 
-    g = orc.Grid(n, n, n, hi=(1.2, 1.2, 1.2), t_end=1.0)
-    s = orc.sedov(g)
-    o = orc.Oracle(g)
-    o.step(s)
+    if threads:
+        orc.set_threads(threads)
+    used = orc.max_threads()
     t0 = time.perf_counter()
     for _ in range(steps):
         rc, _ = o.step(s)
         assert rc == orc.OK
     dt = time.perf_counter() - t0
-    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
-    return n ** 3 * steps / dt, threads, dt
+    return n ** 3 * steps / dt, used, dt
+
+
+def cpu_baseline(n, steps_all, steps_one, sod_reps):
+    """The FP64 oracle on this host: the Sedov n^3 workload on all threads
+    (after one warm-up step) and on one thread, and the whole Sod 64x4x4 run
+    to t = 0.2 (full-run latency)."""
+    from oracle import oracle as orc
+
+    default_threads = orc.max_threads()
+    g = orc.Grid(n, n, n, hi=(1.2, 1.2, 1.2), t_end=1.0)
+    s = orc.sedov(g)
+    o = orc.Oracle(g)
+    o.step(s)
+    say("cpu oracle: all threads")
+    cps, threads, secs = cpu_sedov_leg(o, s, n, steps_all)
+    say("cpu oracle: one thread")
+    cps1, _, secs1 = cpu_sedov_leg(o, s, n, steps_one, threads=1)
+    orc.set_threads(default_threads)
+    o.close()
+    say("cpu oracle: sod latency")
+    gs = orc.Grid(64, 4, 4, hi=(1.0, 0.0625, 0.0625), t_end=0.2)
+    lat, nsteps = [], 0
+    for _ in range(sod_reps + 2):
+        a = time.perf_counter()
+        os_ = orc.sod(gs)
+        osc = orc.Oracle(gs)
+        rc, nsteps = osc.run(os_)
+        b = time.perf_counter()
+        assert rc == orc.DONE
+        osc.close()
+        lat.append(b - a)
+    lat = lat[2:]
+    return {"value": cps, "unit": "cell-updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"{steps_all} FP64 oracle steps of the same {n}^3 Sedov workload on {threads} OpenMP "
+                      f"threads after 1 warm-up step ({secs:.1f} s)",
+            "host": host_cpu(),
+            "one_thread": {"value": cps1, "unit": "cell-updates/s", "cores": 1,
+                           "sample": f"{steps_one} oracle steps of the {n}^3 Sedov workload ({secs1:.1f} s)"},
+            "sod64_latency": {"workload": "sod 64x4x4 to t=0.2, whole oracle run (init + steps)",
+                              "cores": threads, "runs": sod_reps, "steps": nsteps,
+                              "p50_ms": pct(lat, 50) * 1e3, "p99_ms": pct(lat, 99) * 1e3}}
 
 
 def main():
@@ -462,15 +557,13 @@ def main():
         say("batched")
         out["batched"] = batched()
         out["serving"] = serving(a.serve_requests, a.serve_budget_gb)
-    if a.precision_report:
-        say("precision report", a.precision_report)
-        out["precision"] = precision_report(a.precision_report)
+    prec_n = a.precision_report if a.precision_report is not None else (0 if a.quick else 128)
+    if prec_n:
+        say("precision report", prec_n)
+        out["precision"] = precision_report(prec_n)
     if not a.no_cpu:
         say("cpu oracle")
-        cps, threads, secs = cpu_bench(n, a.cpu_steps)
-        out["cpu_baseline"] = {"value": cps, "unit": "cell-updates/s", "cores": threads, "kind": "oracle",
-                               "sample": f"{a.cpu_steps} FP64 oracle steps of the same {n}^3 Sedov "
-                                         f"workload after 1 warm-up step ({secs:.1f} s)"}
+        out["cpu_baseline"] = cpu_baseline(n, a.cpu_steps, a.cpu_steps_one, 50)
     print(json.dumps(out), flush=True)
 
 

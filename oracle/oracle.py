@@ -63,6 +63,10 @@ def lib():
         L.orc_derived.argtypes = [cfg, C.c_void_p, P, P, P, P, P, P, P]
         L.orc_face_swept_volume.restype = C.c_double
         L.orc_face_swept_volume.argtypes = [P, C.c_double, C.c_double]
+        L.orc_max_threads.restype = C.c_int
+        L.orc_max_threads.argtypes = []
+        L.orc_set_threads.restype = None
+        L.orc_set_threads.argtypes = [C.c_int]
         L.orc_vanleer.restype = C.c_double
         L.orc_vanleer.argtypes = [C.c_double, C.c_double]
         L.orc_donor_value.restype = C.c_double
@@ -245,6 +249,16 @@ class Oracle:
         if rc != OK:
             raise ValueError(f"orc_totals: {rc}")
         return m.value, E.value
+
+
+def max_threads() -> int:
+    """OpenMP threads of the oracle's loops in this process."""
+    return int(lib().orc_max_threads())
+
+
+def set_threads(n: int) -> None:
+    """OpenMP threads of this thread's later oracle loops."""
+    lib().orc_set_threads(int(n))
 
 
 def face_swept_volume(d, h1, h2):

@@ -34,6 +34,7 @@
  */
 #define _GNU_SOURCE
 #include <math.h>
+#include <omp.h>
 #include <sys/mman.h>
 #include <stdint.h>
 #include <stdlib.h>
@@ -767,6 +768,14 @@ static int stage_ke_fix_commit(const orc_config *g, orc_ws *W, double *rho, doub
 /* ------------------------------------------------------------------ */
 
 /* Time step of the current state (O3), clipped to t_end - t. */
+/* Threads the OpenMP loops run on (the benchmark reports it beside the
+ * oracle's timings), and a way to change it for the calling thread's later
+ * loops (results do not depend on it). */
+int orc_max_threads(void) { return omp_get_max_threads(); }
+void orc_set_threads(int n) {
+  if (n > 0) omp_set_num_threads(n);
+}
+
 int orc_timestep(const orc_config *g, orc_ws *W, const double *rho, const double *e,
                  const double *u, const double *v, const double *w, double t, double *dt_out) {
   if (!config_valid(g) || !W || W->nx != g->nx || W->ny != g->ny || W->nz != g->nz)
