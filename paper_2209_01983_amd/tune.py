@@ -6,9 +6,13 @@ extent into segments. Results do not depend on the shape; speed does, per
 mesh size and precision. `tune` times every candidate with the library's
 per-kernel event timing on a live run and keeps the fastest; results are
 cached in a JSON file keyed by (GPU architecture, kernel, nx, ny, nz,
-precision). `apply` sets a run's shape from the cache (tuning on a miss if
-asked to).
+precision, remap order, mode, digest of the kernel sources), so an entry
+dies with the kernels it was timed on. The second-order remap's passes have
+a fixed shape, so for remap order 2 only the Lagrange kernel's rows are
+tuned. `apply` sets a run's shape from the cache (tuning on a miss if asked
+to).
 """
+import hashlib
 import json
 import os
 
@@ -29,9 +33,29 @@ def arch():
     return torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
 
 
+_DIGEST = None
+
+
+def source_digest():
+    """Digest of the library's kernel sources (the tile shapes' timings are
+    only as good as the kernels they were measured on)."""
+    global _DIGEST
+    if _DIGEST is None:
+        h = hashlib.sha256()
+        d = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
+        for f in sorted(os.listdir(d)):
+            if f.endswith((".h", ".hip")):
+                with open(os.path.join(d, f), "rb") as fh:
+                    h.update(f.encode() + b"\0" + fh.read())
+        _DIGEST = h.hexdigest()[:16]
+    return _DIGEST
+
+
 def key(gpu_arch, kernel, cfg):
     prec = "fp64" if cfg.precision == sale.SALE_FP64 else "mixed32"
-    return f"{gpu_arch}|{kernel}|{cfg.nx}x{cfg.ny}x{cfg.nz}|{prec}"
+    order = 2 if cfg.remap_order == 2 else 1
+    mode = "lagrangian" if cfg.mode == sale.SALE_LAGRANGIAN else "eulerian"
+    return f"{gpu_arch}|{kernel}|{cfg.nx}x{cfg.ny}x{cfg.nz}|{prec}|order{order}|{mode}|{source_digest()}"
 
 
 def load_cache(path=None):
@@ -71,14 +95,18 @@ def tune(cfg, prob=None, steps=6, warmup=2, rows=ROWS, targets=TARGETS, path=Non
     return the chosen shape (also written to the cache)."""
     run = sale.SaleRun(cfg, prob or sale.sedov_problem())
     times = {}
+    order2 = cfg.remap_order == 2
     for t in targets:
         for r in rows:
-            run.set_launch(r, r, t)
+            # (order 2: the remap passes ignore the remap rows; keep them at 16)
+            run.set_launch(r, 16 if order2 else r, t)
             run.step(warmup)
             ms = run.step_timed(steps)
             times[(r, t)] = (ms[1] / steps, ms[2] / steps)
     run.close()
     best = choose(times)
+    if order2:
+        best["rows_b"] = 16
     if save:
         cache = load_cache(path)
         a = arch()

@@ -144,5 +144,13 @@ def test_tuner_choice_and_cache_round_trip(tmp_path, monkeypatch):
              tune.key("gfx950", "remap", cfg): {"rows": 8, "target": 6144, "ms": 1.0}}
     tune.save_cache(cache, path)
     assert tune.lookup(cfg, path) == {"rows_a": 32, "rows_b": 8, "target": 6144}
-    assert tune.key("gfx950", "remap", cfg) == "gfx950|remap|20x30x40|mixed32"
+    assert tune.key("gfx950", "remap", cfg) == f"gfx950|remap|20x30x40|mixed32|order1|eulerian|{tune.source_digest()}"
     assert tune.lookup(sale.make_config(20, 30, 41), path) is None
+    # remap order and mode are part of the key: an order-2 or Lagrangian run
+    # of the same mesh does not pick up this entry
+    assert tune.lookup(sale.make_config(20, 30, 40, precision=sale.SALE_MIXED32, remap_order=2), path) is None
+    assert tune.lookup(sale.make_config(20, 30, 40, precision=sale.SALE_MIXED32, mode=sale.SALE_LAGRANGIAN),
+                       path) is None
+    # and an entry dies with the kernel sources it was timed on
+    monkeypatch.setattr(tune, "_DIGEST", "0000000000000000")
+    assert tune.lookup(cfg, path) is None
