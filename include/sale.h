@@ -158,24 +158,34 @@ typedef struct {
 typedef struct sale_ctx sale_ctx;
 
 /* Bytes of device workspace one run of `cfg` needs (256-byte aligned
- * sub-buffers). The caller allocates it (e.g. a torch uint8 tensor) and keeps
- * it alive until sale_destroy. SALE_EINVAL for an invalid config. */
+ * sub-buffers): the control block, two copies of the state (rho, e per cell;
+ * u, v, w per node) and the step's intermediates. The caller allocates it
+ * (e.g. a torch uint8 tensor) and keeps it alive until sale_destroy -- the
+ * paper's hand-over of data by pointer, Point_to_data (Sec. III-A).
+ * SALE_EINVAL for an invalid config. */
 int sale_workspace_bytes(const sale_config *cfg, size_t *bytes);
 
 /* Validate cfg and the problem, lay out the workspace d_ws (device,
  * ws_bytes >= sale_workspace_bytes), write the initial state and its first
- * time step on `hip_stream` (asynchronous), and return a new context.
+ * time step on `hip_stream` (asynchronous), and return a new context. The
+ * problems are the paper's verification flows: the Sod tube and the Sedov
+ * blast (Sec. I-D, Fig. 2), the Noh implosion (Sec. I-D), or caller arrays.
  * SALE_USER arrays must be finite with rho > 0 and e >= 0 (SALE_EINVAL
  * otherwise; device arrays are checked on the device and reported by the
  * first sale_status/sale_run). Host user arrays are copied before return. */
 int sale_init(const sale_config *cfg, const sale_problem *prob, void *d_ws, size_t ws_bytes,
               void *hip_stream, sale_ctx **out);
 
-/* Enqueue one Lagrange + remap step (asynchronous). A step enqueued after the
- * run reached t_end, or after an error flag was raised, changes nothing. */
+/* Enqueue one Lagrange + remap step (asynchronous): the Lagrangian phase,
+ * then the Eulerian rezone and advection back to the fixed mesh (the paper's
+ * Lagrangian and Eulerian kernels and advection, Sec. I-D and Table I; in
+ * the pure-Lagrangian mode the Lagrangian rezoning only). A step enqueued
+ * after the run reached t_end, or after an error flag was raised, changes
+ * nothing. */
 int sale_step(sale_ctx *ctx);
 
-/* Run until t >= t_end or until max_steps more steps were taken. t_end < 0
+/* Run until t >= t_end or until max_steps more steps were taken (the
+ * simulation loop of cycles the paper times, Sec. IV). t_end < 0
  * keeps the configured end time; otherwise it replaces it (the last step is
  * clipped to land on it). Steps are enqueued in chunks -- once a context has
  * run 128 steps through sale_run, mostly as replays of a captured HIP graph
@@ -190,8 +200,9 @@ int sale_run(sale_ctx *ctx, double t_end, int64_t max_steps);
  * ascending bit order, to device (dst_on_device != 0) or host memory, in the
  * logical layout. RHO, E, U, V, W are written as double (as_fp64 != 0) or in
  * the storage type (double for SALE_FP64, float for SALE_MIXED32); P and Q
- * are always double. STATE and TOTALS always go to host double arrays.
- * Synchronises the stream. */
+ * are always double. STATE and TOTALS always go to host double arrays. TOTALS
+ * are the mass and the total (internal + kinetic) energy, which the scheme
+ * conserves to rounding. Synchronises the stream. */
 int sale_fields(sale_ctx *ctx, uint32_t mask, void *const *dst, int dst_on_device, int as_fp64);
 
 /* Enqueue n steps like sale_step and time each of the step's three kernels
@@ -212,7 +223,8 @@ int sale_step_timed(sale_ctx *ctx, int32_t n, float ms[3]);
  * SALE_EINVAL for other values. */
 int sale_set_launch(sale_ctx *ctx, int32_t rows_lagrange, int32_t rows_remap, int32_t target_blocks);
 
-/* Synchronise the stream and return the sticky status flags (SALE_FLAG_*).
+/* Synchronise the stream and return the sticky status flags (SALE_FLAG_*)
+ * of the run's steps.
  * Returns SALE_ETANGLE / SALE_ENUMERIC if a flag is set, else SALE_DONE if
  * t >= t_end, else SALE_OK. */
 int sale_status(sale_ctx *ctx, int32_t *status_flags);
@@ -237,20 +249,28 @@ typedef struct sale_pool sale_pool;
 
 /* Create a pool of up to max_runs slots over the device arena
  * [d_arena, d_arena + arena_bytes) (caller-owned, 256-byte aligned, kept alive
- * until sale_pool_destroy); arena_bytes is the pool's memory budget. All runs
- * of a pool share `precision`. */
+ * until sale_pool_destroy); arena_bytes is the pool's device-memory budget
+ * (the admission limit). All runs of a pool share `precision`. Host only: no
+ * device call. (Runs of many independent problems are an addition of this
+ * library: the paper runs one problem per job.) */
 int sale_pool_create(int32_t precision, int32_t max_runs, void *d_arena, size_t arena_bytes,
                      void *hip_stream, sale_pool **out);
 
-/* Admit a run: carve its workspace from the arena, write its initial state
- * (asynchronous) and return its slot. The run stops after n_steps steps or at
- * cfg->t_end, whichever comes first. cfg->precision must equal the pool's.
- * SALE_EBUSY if no slot is free or no free arena range is large enough. */
+/* Admit a run: carve its workspace from the arena, enqueue its initial state
+ * and return its slot. The run stops after n_steps steps or at cfg->t_end,
+ * whichever comes first. cfg->precision must equal the pool's; remap order 1
+ * and SALE_EULERIAN only (SALE_EINVAL otherwise). SALE_EBUSY if no slot is
+ * free or no free arena range is large enough (the caller retries after a
+ * release). Synchronises the stream before returning (the run's descriptor
+ * is copied from host memory), so the admission waits for the work already
+ * on the stream. */
 int sale_pool_admit(sale_pool *pool, const sale_config *cfg, const sale_problem *prob, int64_t n_steps,
                     int32_t *slot);
 
-/* Advance every unfinished admitted run by up to max_steps_per_run steps
- * (asynchronous: lockstep rounds of launches, or one persistent launch). */
+/* Advance every unfinished admitted run by up to max_steps_per_run steps:
+ * lockstep rounds of launches, or one persistent launch. Synchronises the
+ * stream first (the tables of the runs in the advance are copied from host
+ * memory), then enqueues the advance and returns without waiting for it. */
 int sale_pool_advance(sale_pool *pool, int32_t max_steps_per_run);
 
 /* Synchronise the stream and list, in done[0..*n_done), the slots whose run
