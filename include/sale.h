@@ -176,6 +176,35 @@ int sale_workspace_bytes(const sale_config *cfg, size_t *bytes);
 int sale_init(const sale_config *cfg, const sale_problem *prob, void *d_ws, size_t ws_bytes,
               void *hip_stream, sale_ctx **out);
 
+/* Allocation-free variant of sale_init, for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation. The caller passes only the state part of
+ * the workspace -- the control block and the two state buffers, `*state_bytes`
+ * bytes at d_state (device, 256-byte aligned, kept alive until the context
+ * ends); the intermediates (u', the Lagrangian cell results, reduction
+ * partials, the export scratch array, and the second-order / pure-Lagrangian
+ * arrays) live in a device array of the library, 160 MiB (167,772,160 bytes)
+ * per device, which each device holds from its first sale_init_static until
+ * the process ends. Nothing in it needs to start at zero: every intermediate
+ * is written before it is read within a step.
+ * With d_state == NULL the call only writes the state bytes cfg needs to
+ * *state_bytes and returns SALE_OK (no device call). Otherwise *state_bytes
+ * is the size of d_state and the call does what sale_init does and returns
+ * the device's static context. SALE_ENOMEM if cfg's intermediates exceed the
+ * 160 MiB array (first-order cubes up to 137^3 cells in FP64, 166^3 in
+ * MIXED32) or *state_bytes is too small; SALE_EINVAL as
+ * sale_init. Allocates nothing, host or device: the context's host struct is
+ * one static slot per device.
+ * One static context per device: a later sale_init_static on the same device
+ * ends the previous one (its handle must not be used again), and calls on
+ * contexts that share a device's array overlap at their peril -- they race on
+ * it. sale_step, sale_fields, sale_status and sale_run on a static context
+ * allocate nothing either (sale_run enqueues single steps, no graphs);
+ * sale_destroy releases the slot.
+ */
+int sale_init_static(const sale_config *cfg, const sale_problem *prob, void *d_state, size_t *state_bytes,
+                     void *hip_stream, sale_ctx **out);
+
 /* Enqueue one Lagrange + remap step (asynchronous): the Lagrangian phase,
  * then the Eulerian rezone and advection back to the fixed mesh (the paper's
  * Lagrangian and Eulerian kernels and advection, Sec. I-D and Table I; in

@@ -12,7 +12,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsale.so")
-SOURCES = ["sale_step.hip", "sale_remap2.hip", "sale_lagrange.hip", "sale_pool.hip", "sale_api.cpp"]
+SOURCES = ["sale_step.hip", "sale_remap2.hip", "sale_lagrange.hip", "sale_pool.hip", "sale_noalloc.hip",
+           "sale_api.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -8,6 +8,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <new>
 
 #include "../../include/sale.h"
@@ -35,6 +36,10 @@ struct sale_ctx {
   hipStream_t cap_stream = nullptr;
   hipGraphExec_t graph[2] = {nullptr, nullptr};
   long long enqueued = 0;  // steps enqueued through sale_run
+  // a context of sale_init_static: intermediates in the library's device
+  // array, host storage in a static table, no step graphs (every call on it
+  // allocates nothing)
+  bool is_static = false;
   ~sale_ctx() {
     for (int k = 0; k < 2; k++)
       if (graph[k]) (void)hipGraphExecDestroy(graph[k]);
@@ -239,7 +244,7 @@ hipError_t step_graph(sale_ctx *x, int par, hipGraphExec_t *out) {
 // n steps on the context's stream: whole graphs, then single steps (only
 // single steps while the context is young).
 hipError_t enqueue_steps(sale_ctx *x, int64_t n) {
-  const bool graphs = x->enqueued >= kGraphAfter;
+  const bool graphs = x->enqueued >= kGraphAfter && !x->is_static;
   x->enqueued += n;
   for (; graphs && n >= kGraphSteps; n -= kGraphSteps) {
     hipGraphExec_t g;
@@ -349,6 +354,51 @@ int fields_impl(const Mesh &m, int precision, const Work<double> &w64, const Wor
   return SALE_OK;
 }
 
+// Set up context x (fresh) on the state part `state` and the intermediates
+// `inter` (validated config and problem), and enqueue the initial state.
+int init_ctx(sale_ctx *x, const sale_config *cfg, const sale_problem *prob, const Mesh &m, void *state,
+             void *inter, void *hip_stream) {
+  x->cfg = *cfg;
+  x->m = m;
+  // a mesh at most 4 cells across in y fits one row of 8-row remap tiles,
+  // whose 4-wave blocks pass their barriers sooner (a Sod tube 64x4x4 runs
+  // 3% faster)
+  if (m.ny <= 4) x->L.rows_b = 8;
+  x->stream = (hipStream_t)hip_stream;
+  x->ws = state;
+  x->ws_bytes = 0;
+  x->t_end = cfg->t_end;
+  x->precision = cfg->precision;
+  x->cur = 0;
+  hipError_t e;
+  if (x->precision == SALE_FP64) {
+    sale::layout_split<double>(m, state, inter, &x->ctl, &x->w64);
+    e = init_problem<double>(m, x->ctl, x->w64, prob, x->t_end, x->stream);
+    if (e == hipSuccess && m.mode == 1) e = sale::launch_lag_init(m, x->ctl, x->w64, x->stream);
+  } else {
+    sale::layout_split<float>(m, state, inter, &x->ctl, &x->w32);
+    e = init_problem<float>(m, x->ctl, x->w32, prob, x->t_end, x->stream);
+  }
+  return e == hipSuccess ? SALE_OK : hip_fail(e, "sale_init");
+}
+
+// Host storage of the sale_init_static contexts: one per device, built in
+// place (no allocation), released by sale_destroy or by the next
+// sale_init_static on the same device.
+constexpr int kMaxStaticDevices = 64;
+alignas(sale_ctx) unsigned char g_static_mem[kMaxStaticDevices][sizeof(sale_ctx)];
+sale_ctx *g_static_ctx[kMaxStaticDevices];
+std::mutex g_static_mu;
+
+void release_static(sale_ctx *x) {
+  std::lock_guard<std::mutex> lock(g_static_mu);
+  for (int d = 0; d < kMaxStaticDevices; d++)
+    if (g_static_ctx[d] == x) {
+      x->~sale_ctx();
+      g_static_ctx[d] = nullptr;
+    }
+}
+
 }  // namespace sale_host
 
 using namespace sale_host;
@@ -381,31 +431,52 @@ int sale_init(const sale_config *cfg, const sale_problem *prob, void *d_ws, size
   if (ws_bytes < ws_bytes_for(m, cfg->precision)) return SALE_ENOMEM;
   sale_ctx *x = new (std::nothrow) sale_ctx;
   if (!x) return SALE_ENOMEM;
-  x->cfg = *cfg;
-  x->m = m;
-  // a mesh at most 4 cells across in y fits one row of 8-row remap tiles,
-  // whose 4-wave blocks pass their barriers sooner (a Sod tube 64x4x4 runs
-  // 3% faster)
-  if (m.ny <= 4) x->L.rows_b = 8;
-  x->stream = (hipStream_t)hip_stream;
-  x->ws = d_ws;
-  x->ws_bytes = ws_bytes;
-  x->t_end = cfg->t_end;
-  x->precision = cfg->precision;
-  x->cur = 0;
-  hipError_t e;
-  if (x->precision == SALE_FP64) {
-    sale::layout<double>(m, d_ws, &x->ctl, &x->w64);
-    e = init_problem<double>(m, x->ctl, x->w64, prob, x->t_end, x->stream);
-    if (e == hipSuccess && m.mode == 1) e = sale::launch_lag_init(m, x->ctl, x->w64, x->stream);
-  } else {
-    sale::layout<float>(m, d_ws, &x->ctl, &x->w32);
-    e = init_problem<float>(m, x->ctl, x->w32, prob, x->t_end, x->stream);
-  }
-  if (e != hipSuccess) {
+  const size_t sb = cfg->precision == SALE_FP64 ? sale::state_bytes<double>(m) : sale::state_bytes<float>(m);
+  if ((rc = init_ctx(x, cfg, prob, m, d_ws, (char *)d_ws + sb, hip_stream)) != SALE_OK) {
     delete x;
-    return hip_fail(e, "sale_init");
+    return rc;
   }
+  *out = x;
+  return SALE_OK;
+}
+
+int sale_init_static(const sale_config *cfg, const sale_problem *prob, void *d_state, size_t *state_bytes,
+                     void *hip_stream, sale_ctx **out) {
+  if (!state_bytes) return SALE_EINVAL;
+  if (out) *out = nullptr;
+  int rc = validate_config(cfg);
+  if (rc != SALE_OK) return rc;
+  const Mesh m = make_mesh(cfg);
+  const bool fp64 = cfg->precision == SALE_FP64;
+  const size_t need = fp64 ? sale::state_bytes<double>(m) : sale::state_bytes<float>(m);
+  const size_t inter = fp64 ? sale::inter_bytes<double>(m) : sale::inter_bytes<float>(m);
+  if (inter > sale::kStaticScratchBytes) return SALE_ENOMEM;  // beyond the library's device array
+  if (!d_state) {  // size query
+    *state_bytes = need;
+    return SALE_OK;
+  }
+  if (!out) return SALE_EINVAL;
+  if ((rc = validate_problem(prob, m)) != SALE_OK) return rc;
+  if (((uintptr_t)d_state & 255u)) return SALE_EINVAL;
+  if (*state_bytes < need) return SALE_ENOMEM;
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxStaticDevices) return SALE_EINVAL;
+  void *scr = nullptr;
+  HIP_TRY(sale::static_scratch(&scr));
+  std::lock_guard<std::mutex> lock(g_static_mu);
+  sale_ctx *x = g_static_ctx[dev];
+  if (x) {  // the device's previous static context ends here
+    x->~sale_ctx();
+    g_static_ctx[dev] = nullptr;
+  }
+  x = new (g_static_mem[dev]) sale_ctx;
+  x->is_static = true;
+  if ((rc = init_ctx(x, cfg, prob, m, d_state, scr, hip_stream)) != SALE_OK) {
+    x->~sale_ctx();
+    return rc;
+  }
+  g_static_ctx[dev] = x;
   *out = x;
   return SALE_OK;
 }
@@ -467,7 +538,12 @@ int sale_fields(sale_ctx *x, uint32_t mask, void *const *dst, int dst_on_device,
                      as_fp64);
 }
 
-void sale_destroy(sale_ctx *x) { delete x; }
+void sale_destroy(sale_ctx *x) {
+  if (x && x->is_static)
+    sale_host::release_static(x);
+  else
+    delete x;
+}
 
 const char *sale_strerror(int code) {
   switch (code) {

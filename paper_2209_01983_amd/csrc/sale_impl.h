@@ -161,8 +161,21 @@ constexpr int kStepThreads = 512;  // block size of the 16-row tiles (and of the
 
 template <typename R>
 size_t workspace_bytes(const Mesh &m);
+// the state part (control block, two state buffers) and the intermediates
+template <typename R>
+size_t state_bytes(const Mesh &m);
+template <typename R>
+size_t inter_bytes(const Mesh &m);
 template <typename R>
 void layout(const Mesh &m, void *ws, Ctl **ctl, Work<R> *w);
+template <typename R>
+void layout_split(const Mesh &m, void *state, void *inter, Ctl **ctl, Work<R> *w);
+
+// The library's device array for the intermediates of sale_init_static
+// contexts (sale_noalloc.hip): its size, and its address on the current
+// device (looked up once per device).
+constexpr size_t kStaticScratchBytes = size_t(160) << 20;
+hipError_t static_scratch(void **ptr);
 
 // Initial states into w.s[0] (asynchronous on `s`).
 template <typename R>

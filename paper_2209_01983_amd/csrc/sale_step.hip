@@ -391,24 +391,39 @@ bool launch_valid(const Launch &L) {
 // ---- workspace layout -----------------------------------------------------------------
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// The workspace is two parts: the state part (control block and the two
+// state buffers) and the intermediates (u', the Lagrangian cell results,
+// reduction partials, the scratch array, and the second-order and
+// pure-Lagrangian arrays). A single-run workspace holds both back to back;
+// sale_init_static puts the intermediates in the library's device array.
 template <typename R>
-size_t workspace_bytes(const Mesh &m) {
+size_t state_bytes(const Mesh &m) {
+  const size_t cR = align256((size_t)m.ncell * sizeof(R)), nR = align256((size_t)m.nnode * sizeof(R));
+  return align256(sizeof(Ctl)) + 2 * (2 * cR + 3 * nR);
+}
+
+template <typename R>
+size_t inter_bytes(const Mesh &m) {
   const size_t cR = align256((size_t)m.ncell * sizeof(R)), nR = align256((size_t)m.nnode * sizeof(R));
   const size_t sD = align256((size_t)(m.ncell > m.nnode ? m.ncell : m.nnode) * sizeof(double));
-  // ctl | 2 states | u' | e^L | 3 swept volumes | partials | scratch
+  // u' | e^L | 3 swept volumes | partials | scratch
   // (+ rho^L and the second-order remap's intermediates for order 2)
   const size_t r2 = m.order == 2 ? 6 * cR + nR : 0;
   const size_t cD = align256((size_t)m.ncell * sizeof(double)), nD = align256((size_t)m.nnode * sizeof(double));
   const size_t lg = m.mode == 1 ? 6 * nD + 25 * cD : 0;  // positions x2, masses, corner forces
-  return align256(sizeof(Ctl)) + 2 * (2 * cR + 3 * nR) + 3 * nR + cR + 3 * cR +
-         align256(3 * TOT_BLOCKS * sizeof(double)) + sD + r2 + lg;
+  return 3 * nR + cR + 3 * cR + align256(3 * TOT_BLOCKS * sizeof(double)) + sD + r2 + lg;
 }
 
 template <typename R>
-void layout(const Mesh &m, void *ws, Ctl **ctl, Work<R> *w) {
+size_t workspace_bytes(const Mesh &m) {
+  return state_bytes<R>(m) + inter_bytes<R>(m);
+}
+
+template <typename R>
+void layout_split(const Mesh &m, void *state, void *inter, Ctl **ctl, Work<R> *w) {
   const size_t cR = align256((size_t)m.ncell * sizeof(R)), nR = align256((size_t)m.nnode * sizeof(R));
   const size_t sD = align256((size_t)(m.ncell > m.nnode ? m.ncell : m.nnode) * sizeof(double));
-  char *p = (char *)ws;
+  char *p = (char *)state;
   *ctl = (Ctl *)p;
   p += align256(sizeof(Ctl));
   auto takeR = [&](size_t b) {
@@ -428,6 +443,7 @@ void layout(const Mesh &m, void *ws, Ctl **ctl, Work<R> *w) {
     w->s[a].v = takeR(nR);
     w->s[a].w = takeR(nR);
   }
+  p = (char *)inter;
   w->up = takeR(nR);
   w->vp = takeR(nR);
   w->wp = takeR(nR);
@@ -457,6 +473,11 @@ void layout(const Mesh &m, void *ws, Ctl **ctl, Work<R> *w) {
     w->lg.m = takeD(cD);
     w->lg.F = takeD(24 * cD);
   }
+}
+
+template <typename R>
+void layout(const Mesh &m, void *ws, Ctl **ctl, Work<R> *w) {
+  layout_split<R>(m, ws, (char *)ws + state_bytes<R>(m), ctl, w);
 }
 
 // ---- launchers ----------------------------------------------------------------------------
@@ -606,7 +627,10 @@ hipError_t launch_export(const Mesh &m, const Work<R> &w, int cur, int which, do
 
 #define SALE_INSTANTIATE(R)                                                                              \
   template size_t workspace_bytes<R>(const Mesh &);                                                      \
+  template size_t state_bytes<R>(const Mesh &);                                                          \
+  template size_t inter_bytes<R>(const Mesh &);                                                          \
   template void layout<R>(const Mesh &, void *, Ctl **, Work<R> *);                                      \
+  template void layout_split<R>(const Mesh &, void *, void *, Ctl **, Work<R> *);                        \
   template hipError_t launch_init_sod<R>(const Mesh &, Ctl *, const Work<R> &, const double[5], double,  \
                                          long long, double, hipStream_t);                                \
   template hipError_t launch_init_sedov<R>(const Mesh &, Ctl *, const Work<R> &, const double[3], double, \

@@ -38,7 +38,7 @@ CELL_FIELDS = ("rho", "e", "p", "q")
 NODE_FIELDS = ("u", "v", "w", "x", "y", "z")
 
 # functions the header declares (checked by the tests against include/sale.h)
-EXPORTS = ("sale_workspace_bytes", "sale_init", "sale_step", "sale_run", "sale_fields",
+EXPORTS = ("sale_workspace_bytes", "sale_init", "sale_init_static", "sale_step", "sale_run", "sale_fields",
            "sale_step_timed", "sale_set_launch", "sale_status", "sale_destroy", "sale_strerror")
 POOL_EXPORTS = ("sale_pool_create", "sale_pool_admit", "sale_pool_advance", "sale_pool_poll",
                 "sale_pool_fields", "sale_pool_release", "sale_pool_destroy")
@@ -83,6 +83,9 @@ def lib():
         L.sale_workspace_bytes.restype = C.c_int
         L.sale_init.argtypes = [cp, pp, C.c_void_p, C.c_size_t, C.c_void_p, C.POINTER(C.c_void_p)]
         L.sale_init.restype = C.c_int
+        L.sale_init_static.argtypes = [cp, pp, C.c_void_p, C.POINTER(C.c_size_t), C.c_void_p,
+                                       C.POINTER(C.c_void_p)]
+        L.sale_init_static.restype = C.c_int
         L.sale_step.argtypes = [C.c_void_p]
         L.sale_step.restype = C.c_int
         L.sale_run.argtypes = [C.c_void_p, C.c_double, C.c_int64]
@@ -134,6 +137,16 @@ def sale_init(cfg: sale_config, prob: sale_problem, d_ws: int, ws_bytes: int, st
     rc = lib().sale_init(C.byref(cfg), C.byref(prob), C.c_void_p(d_ws), ws_bytes, C.c_void_p(stream),
                          C.byref(ctx))
     return rc, (ctx if rc == SALE_OK else None)
+
+
+def sale_init_static(cfg: sale_config, prob: sale_problem, d_state, state_bytes: int, stream: int):
+    """Returns (code, ctx handle or None, state bytes). With d_state None: the
+    size query (code, None, bytes cfg needs)."""
+    ctx = C.c_void_p(None)
+    n = C.c_size_t(state_bytes)
+    rc = lib().sale_init_static(C.byref(cfg), C.byref(prob), C.c_void_p(d_state), C.byref(n),
+                                C.c_void_p(stream), C.byref(ctx))
+    return rc, (ctx if rc == SALE_OK and d_state else None), n.value
 
 
 def sale_step(ctx) -> int:
@@ -290,20 +303,29 @@ def _field_buffers(torch, device, names, cell_shape, node_shape, on_device):
 
 class SaleRun:
     """One run: workspace as a torch uint8 tensor on `device`, torch's current
-    stream as the library's stream."""
+    stream as the library's stream. With static=True the context comes from
+    sale_init_static: the tensor holds only the state part of the workspace,
+    the intermediates live in the library's device array."""
 
-    def __init__(self, cfg: sale_config, prob: sale_problem, device="cuda:0", keepalive=None):
+    def __init__(self, cfg: sale_config, prob: sale_problem, device="cuda:0", keepalive=None, static=False):
         import torch
         self.torch = torch
         self.cfg = cfg
         self.device = torch.device(device)
-        self.nbytes = sale_workspace_bytes(cfg)
-        self.ws = torch.empty(self.nbytes, dtype=torch.uint8, device=self.device)
         self.stream = torch.cuda.current_stream(self.device).cuda_stream
-        rc, self.ctx = sale_init(cfg, prob, self.ws.data_ptr(), self.nbytes, self.stream)
+        if static:
+            rc, _, self.nbytes = sale_init_static(cfg, prob, None, 0, self.stream)
+            if rc != SALE_OK:
+                raise SaleError(rc, "sale_init_static")
+            self.ws = torch.empty(self.nbytes, dtype=torch.uint8, device=self.device)
+            rc, self.ctx, _ = sale_init_static(cfg, prob, self.ws.data_ptr(), self.nbytes, self.stream)
+        else:
+            self.nbytes = sale_workspace_bytes(cfg)
+            self.ws = torch.empty(self.nbytes, dtype=torch.uint8, device=self.device)
+            rc, self.ctx = sale_init(cfg, prob, self.ws.data_ptr(), self.nbytes, self.stream)
         del keepalive
         if rc != SALE_OK:
-            raise SaleError(rc, "sale_init")
+            raise SaleError(rc, "sale_init_static" if static else "sale_init")
         self.cell_shape = (cfg.nz, cfg.ny, cfg.nx)
         self.node_shape = (cfg.nz + 1, cfg.ny + 1, cfg.nx + 1)
 
