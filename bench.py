@@ -97,13 +97,13 @@ def algorithmic_bytes(n, esz=8):
 
 def compulsory_bytes(n, esz=8):
     """What each step kernel must move given its inputs and outputs (R = esz
-    bytes; swept volumes always FP64): Lagrange+geometry reads rho, e, u, v, w
-    and writes u', v', w', rho^L, e^L and three swept volumes per cell; remap
-    reads rho^L, e^L, the swept volumes, rho and u', v', w' and writes rho, e,
-    u, v, w."""
+    bytes, the storage type of the state and the hand-off): Lagrange reads
+    rho, e, u, v, w and writes u', v', w', e^L and the three lower-face swept
+    volumes per cell; remap reads e^L, the swept volumes, rho and u', v', w'
+    and writes rho, e, u, v, w."""
     c, p = n ** 3, (n + 1) ** 3
-    lag = c * (2 * esz) + p * (3 * esz) + p * (3 * esz) + c * (2 * esz + 3 * 8)
-    rem = c * (3 * esz + 3 * 8) + p * (3 * esz) + c * (2 * esz) + p * (3 * esz)
+    lag = c * (2 * esz) + p * (3 * esz) + p * (3 * esz) + c * (4 * esz)
+    rem = c * (4 * esz) + c * esz + p * (3 * esz) + c * (2 * esz) + p * (3 * esz)
     return {"k_lagrange": lag, "k_remap": rem}
 
 
