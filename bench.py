@@ -146,7 +146,7 @@ def headline(n, steps, warmup, precision, tuned=True, fixed=None, order=1):
     from paper_2209_01983_amd import sale, tune
 
     cfg = sale.make_config(n, n, n, hi=(1.2, 1.2, 1.2), t_end=1.0, precision=precision, remap_order=order)
-    shape = {"rows_a": 16, "rows_b": 16, "target": 0}
+    shape = {"rows_a": 14, "rows_b": 14, "target": 0}
     if fixed:
         shape = dict(zip(("rows_a", "rows_b", "target"), fixed))
     elif tuned:

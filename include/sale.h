@@ -243,9 +243,9 @@ int sale_fields(sale_ctx *ctx, uint32_t mask, void *const *dst, int dst_on_devic
 int sale_step_timed(sale_ctx *ctx, int32_t n, float ms[3]);
 
 /* Launch shape of the context's two step kernels (a tuning knob; results do
- * not depend on it): tiles of 32 x rows columns for the Lagrangian kernel and
- * the remap kernel (rows 8, 12, 16, 24 or 32; default 16 and 16, the remap
- * 8 on meshes at most 4 cells across in y), and the
+ * not depend on it): tiles of 36 x rows columns (32 owned in x) for the
+ * Lagrangian kernel and the remap kernel (rows 7, 14 or 28; default 14 and
+ * 14, the remap 7 on meshes at most 3 cells across in y), and the
  * number of blocks the split of the z extent into segments aims at (0, the
  * default: automatic -- a small mesh is split as finely as the chip holds its
  * blocks at once, a large one aims at 3072 blocks). Synchronises the stream.

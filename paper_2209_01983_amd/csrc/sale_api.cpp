@@ -360,10 +360,9 @@ int init_ctx(sale_ctx *x, const sale_config *cfg, const sale_problem *prob, cons
              void *inter, void *hip_stream) {
   x->cfg = *cfg;
   x->m = m;
-  // a mesh at most 4 cells across in y fits one row of 8-row remap tiles,
-  // whose 4-wave blocks pass their barriers sooner (a Sod tube 64x4x4 runs
-  // 3% faster)
-  if (m.ny <= 4) x->L.rows_b = 8;
+  // a mesh at most 3 cells across in y fits one row of 7-row remap tiles,
+  // whose 4-wave blocks pass their barriers sooner
+  if (m.ny <= 3) x->L.rows_b = 7;
   x->stream = (hipStream_t)hip_stream;
   x->ws = state;
   x->ws_bytes = 0;

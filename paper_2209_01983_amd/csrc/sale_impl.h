@@ -126,7 +126,8 @@ hipError_t launch_positions(const Mesh &m, const Work<R> &w, int cur, int axis, 
 template <typename R>
 hipError_t launch_remap2(const Mesh &m, Ctl *ctl, const Work<R> &w, int cur, hipStream_t s);
 
-// Launch decomposition of a z-marching step kernel: tiles of 32 x CH columns,
+// Launch decomposition of a z-marching step kernel: tiles of 36 x CH columns
+// (32 owned in x),
 // the z extent split into segments so that the grid fills the chip.
 struct Grid2 {
   int tx, ty, nseg, seglen;  // tiles per axis, z segments, planes per segment
@@ -146,11 +147,11 @@ struct RunArgs {
 };
 
 // Launch shape of the two z-marching kernels of a single run: tile rows
-// (tiles are 32 x rows columns, one thread per column; rows 8, 16 or 32) and
+// (tiles are 36 x rows columns, one thread per column; rows 7, 14 or 28) and
 // the number of blocks the z segmentation aims at.
 struct Launch {
-  int rows_a = 16;     // Lagrange + geometry kernel
-  int rows_b = 16;     // remap kernel
+  int rows_a = 14;     // Lagrange + geometry kernel
+  int rows_b = 14;     // remap kernel
   int target = 0;      // blocks per kernel the z split aims at (0: automatic)
 };
 bool launch_valid(const Launch &L);
@@ -233,9 +234,9 @@ struct PoolQueue {
   unsigned int abort;       // set by a timed-out wait: later waits give up at once
 };
 
-// Tile rows of the persistent kernel (its tiles are 32 x kPoolRows columns).
+// Tile rows of the multi-run kernels (their tiles are 36 x kPoolRows columns).
 #ifndef SALE_POOL_ROWS
-#define SALE_POOL_ROWS 16
+#define SALE_POOL_ROWS 14
 #endif
 constexpr int kPoolRows = SALE_POOL_ROWS;
 

@@ -36,13 +36,13 @@ namespace {
 
 constexpr int CH = kPoolRows;
 // register cap of the lockstep tile kernels: that of the single-run kernels
-// of the same tile rows (4 waves per SIMD for 16 rows)
-constexpr int waves_of_lock() { return CH == 12 || CH == 24 ? 3 : 4; }
-// the FP32 bulk remap tile of 16 rows fits 80 VGPRs and 40 KB of LDS: three
+// of the same tile rows (4 waves per SIMD)
+constexpr int waves_of_lock() { return 4; }
+// the FP32 bulk remap tile of 14 rows fits 80 VGPRs and 42 KB of LDS: three
 // blocks per CU
 template <typename R>
-constexpr int waves_of_lock_remap() { return sizeof(R) == 4 && CH == 16 ? 6 : waves_of_lock(); }
-constexpr int NT = 32 * CH;
+constexpr int waves_of_lock_remap() { return sizeof(R) == 4 && CH == 14 ? 6 : waves_of_lock(); }
+constexpr int NT = tile_threads<CH>();
 constexpr int LDS_DOUBLES =
     lagrange_lds_doubles<CH>() > remap_lds_doubles<double, CH>() ? lagrange_lds_doubles<CH>()
                                                                  : remap_lds_doubles<double, CH>();

@@ -7,24 +7,26 @@
 namespace sale {
 namespace {
 
-// The two z-marching kernels are templates on their tile shape (32 x CH
-// columns, one thread each); the launch shape picks CH per kernel at run time.
-// Each shape has a register cap (minimum waves per SIMD): a block of 32 x CH
-// threads puts CH / 8 waves on each SIMD, so the cap fixes how many blocks
-// share a CU. Register spills are to be avoided: their reloads wait for every
-// outstanding global load and store of the wave.
-#ifndef SALE_WAVES_16
-#define SALE_WAVES_16 4
+// The two z-marching kernels are templates on their tile rows CH (tiles of
+// kTileW x CH columns, one thread each, in blocks of tile_threads<CH>()); the
+// launch shape picks CH per kernel at run time: 7, 14 or 28 rows (256, 512,
+// 1024 threads). Each shape has a register cap (minimum waves per SIMD): a
+// block of 512 threads puts 2 waves on each SIMD, so the cap fixes how many
+// blocks share a CU. Register spills are to be avoided: their reloads wait
+// for every outstanding global load and store of the wave.
+#ifndef SALE_WAVES_14
+#define SALE_WAVES_14 4
 #endif
 template <int CH>
 constexpr int waves_of() {
-  return CH == 12 ? 3 : CH == 24 ? 3 : CH == 16 ? SALE_WAVES_16 : 4;
+  return CH == 14 ? SALE_WAVES_14 : 4;
 }
-// The FP32 bulk remap tile of 16 rows fits 80 VGPRs and its LDS (bulk planes
-// as float) 40 KB: three blocks per CU.
+// The FP32 bulk remap tile of 14 rows fits 80 VGPRs and its LDS (bulk planes
+// as float) 42 KB: three blocks per CU.
+// (The FP64 remap tile of 7 rows needs 41 KB of LDS: three blocks per CU.)
 template <typename R, int CH>
 constexpr int remap_waves() {
-  return sizeof(R) == 4 && CH == 16 ? 6 : waves_of<CH>();
+  return sizeof(R) == 4 && CH == 14 ? 6 : sizeof(R) == 8 && CH == 7 ? 3 : waves_of<CH>();
 }
 constexpr int TPB = 256;  // simple per-element kernels
 
@@ -36,7 +38,7 @@ __global__ void k_begin(Mesh m, Ctl *ctl) {
 }
 
 template <typename R, int CH>
-__global__ __launch_bounds__(32 * CH, waves_of<CH>()) void k_lagrange(RunArgs<R> a) {
+__global__ __launch_bounds__(tile_threads<CH>(), waves_of<CH>()) void k_lagrange(RunArgs<R> a) {
   __shared__ double lds[lagrange_lds_doubles<CH>()];
   if (a.ctl->done) return;
   const bool t = lagrange_tile<R, CH>(a, xcd_logical_block(blockIdx.x, gridDim.x), a.ctl->dt, lds);
@@ -44,7 +46,7 @@ __global__ __launch_bounds__(32 * CH, waves_of<CH>()) void k_lagrange(RunArgs<R>
 }
 
 template <typename R, int CH>
-__global__ __launch_bounds__(32 * CH, (remap_waves<R, CH>())) void k_remap(RunArgs<R> a) {
+__global__ __launch_bounds__(tile_threads<CH>(), (remap_waves<R, CH>())) void k_remap(RunArgs<R> a) {
   __shared__ double lds[remap_lds_doubles<R, CH>()];
   const int b = xcd_logical_block(blockIdx.x, gridDim.x);
   if (a.ctl->done) {
@@ -54,7 +56,7 @@ __global__ __launch_bounds__(32 * CH, (remap_waves<R, CH>())) void k_remap(RunAr
   double amax;
   bool bad, tangle;
   remap_tile<R, CH>(a, b, lds, &amax, &bad, &tangle);
-  block_max_to_ctl<32 * CH>(a.ctl, amax, bad);
+  block_max_to_ctl<tile_threads<CH>()>(a.ctl, amax, bad);
   if (tangle) atomicOr(&a.ctl->status, SALE_FLAG_TANGLE);
 }
 
@@ -370,21 +372,20 @@ Grid2 make_grid(int nx, int ny, int nplanes, int tile_x, int tile_y, int target_
 // blocks of a step kernel resident on MI355X at once (256 CUs), by tile rows
 static int resident_blocks(int rows) {
   switch (rows) {
-    case 8: return 4 * 256;
-    case 12:
-    case 16: return 2 * 256;
+    case 7: return 4 * 256;
+    case 14: return 2 * 256;
     default: return 256;
   }
 }
 Grid2 grid_lagrange(const Mesh &m, int target_blocks, int rows) {
-  return make_grid(m.nx, m.ny, m.nz, 32 - 3, rows - 3, target_blocks, 3, resident_blocks(rows));
+  return make_grid(m.nx, m.ny, m.nz, kTileX, rows - 3, target_blocks, 3, resident_blocks(rows));
 }
 Grid2 grid_remap(const Mesh &m, int target_blocks, int rows) {
-  return make_grid(m.nx, m.ny, m.nz, 32 - 4, rows - 4, target_blocks, 4, resident_blocks(rows));
+  return make_grid(m.nx, m.ny, m.nz, kTileX, rows - 4, target_blocks, 4, resident_blocks(rows));
 }
 
 bool launch_valid(const Launch &L) {
-  auto ok = [](int r) { return r == 8 || r == 12 || r == 16 || r == 24 || r == 32; };
+  auto ok = [](int r) { return r == 7 || r == 14 || r == 28; };
   return ok(L.rows_a) && ok(L.rows_b) && L.target >= 0 && L.target <= (1 << 20);
 }
 
@@ -556,11 +557,11 @@ RunArgs<R> run_args(const Mesh &m, Ctl *ctl, const Work<R> &w, int cur, const La
 
 template <typename R, int CH>
 void launch_lagrange(const RunArgs<R> &a, hipStream_t s) {
-  hipLaunchKernelGGL((k_lagrange<R, CH>), dim3(a.ga.blocks()), dim3(32 * CH), 0, s, a);
+  hipLaunchKernelGGL((k_lagrange<R, CH>), dim3(a.ga.blocks()), dim3(tile_threads<CH>()), 0, s, a);
 }
 template <typename R, int CH>
 void launch_remap(const RunArgs<R> &a, hipStream_t s) {
-  hipLaunchKernelGGL((k_remap<R, CH>), dim3(a.gb.blocks()), dim3(32 * CH), 0, s, a);
+  hipLaunchKernelGGL((k_remap<R, CH>), dim3(a.gb.blocks()), dim3(tile_threads<CH>()), 0, s, a);
 }
 
 template <typename R>
@@ -579,11 +580,9 @@ hipError_t launch_step(const Mesh &m, Ctl *ctl, const Work<R> &w, int cur, const
   hipLaunchKernelGGL(k_begin, dim3(1), dim3(64), 0, s, m, ctl);
   if (ev && e == hipSuccess) e = hipEventRecord(ev[1], s);
   switch (L.rows_a) {
-    case 8: launch_lagrange<R, 8>(a, s); break;
-    case 12: launch_lagrange<R, 12>(a, s); break;
-    case 24: launch_lagrange<R, 24>(a, s); break;
-    case 32: launch_lagrange<R, 32>(a, s); break;
-    default: launch_lagrange<R, 16>(a, s); break;
+    case 7: launch_lagrange<R, 7>(a, s); break;
+    case 28: launch_lagrange<R, 28>(a, s); break;
+    default: launch_lagrange<R, 14>(a, s); break;
   }
   if (ev && e == hipSuccess) e = hipEventRecord(ev[2], s);
   if (m.order == 2) {
@@ -591,11 +590,9 @@ hipError_t launch_step(const Mesh &m, Ctl *ctl, const Work<R> &w, int cur, const
     if (r != hipSuccess) return r;
   } else {
     switch (L.rows_b) {
-      case 8: launch_remap<R, 8>(a, s); break;
-      case 12: launch_remap<R, 12>(a, s); break;
-      case 24: launch_remap<R, 24>(a, s); break;
-      case 32: launch_remap<R, 32>(a, s); break;
-      default: launch_remap<R, 16>(a, s); break;
+      case 7: launch_remap<R, 7>(a, s); break;
+      case 28: launch_remap<R, 28>(a, s); break;
+      default: launch_remap<R, 14>(a, s); break;
     }
   }
   if (ev && e == hipSuccess) e = hipEventRecord(ev[3], s);

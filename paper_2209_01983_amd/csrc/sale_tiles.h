@@ -16,8 +16,8 @@
 //                  M, rho^{n+1}, e^pre, dual-mesh momentum / KE remap,
 //                  u^{n+1}, KE fix, e^{n+1}, next signal speed
 //
-// A tile is a 32 x CH grid of (x, y) columns, one thread per column, marched
-// along z over one z segment one plane at a time. A plane's values live in
+// A tile is a kTileW x CH grid of (x, y) columns (36 x 14 by default), one
+// thread per column, marched along z over one z segment one plane at a time. A plane's values live in
 // LDS while its x/y neighbours need them; values a column needs again one or
 // two planes later stay in that column's registers; global loads run one
 // plane ahead. The hand-off between the two tiles is u' (per node) and the
@@ -125,15 +125,33 @@ __device__ __forceinline__ void tile_of(const Grid2 &g, int b, int &tx, int &ty,
   seg = r / g.ty;
 }
 
-// LDS doubles needed by each tile function for a 32 x CH tile
+// Tile geometry. A tile is kTileW = 36 columns in x by CH rows in y, of which
+// the middle kTileX = 32 in x are owned: a row of a tile's owned cells is a
+// whole number of 128-byte lines (32 doubles or floats, on meshes whose x
+// extent is a multiple of 16 cells), so neighbouring tiles never write parts
+// of the same line (a line written in parts by two blocks costs the memory
+// system far more than whole lines) and 320 cells split into 10 tiles. The
+// block rounds the 36 x CH threads up to a multiple of 64; the spare threads
+// map to an LDS row CH of their own and own nothing, so every wave is whole
+// and every thread meets every barrier.
+constexpr int kTileW = 36, kTileX = 32;
+template <int CH>
+constexpr int tile_threads() {
+  return (kTileW * CH + 63) / 64 * 64;
+}
+static_assert(tile_threads<7>() - kTileW * 7 < kTileW && tile_threads<14>() - kTileW * 14 < kTileW &&
+                  tile_threads<28>() - kTileW * 28 < kTileW,
+              "the spare threads of a block fit in one LDS row");
+
+// LDS doubles needed by each tile function (planes of kTileW x (CH + 1))
 template <int CH>
 constexpr int lagrange_lds_doubles() {
-  return 11 * 32 * CH;
+  return 11 * kTileW * (CH + 1);
 }
 // (remap: two double planes, then 16 planes of the bulk type R)
 template <typename R, int CH>
 constexpr int remap_lds_doubles() {
-  return (2 * 8 + 16 * (int)sizeof(R)) * 32 * CH / 8;
+  return (2 * 8 + 16 * (int)sizeof(R)) * kTileW * (CH + 1) / 8;
 }
 
 // ---------------------------------------------------------------------------------
@@ -141,7 +159,8 @@ constexpr int remap_lds_doubles() {
 // ---------------------------------------------------------------------------------
 // Column (ci, cj) is node column / cell column (X0 + ci - 1, Y0 + cj - 1). The
 // tile owns cells [X0, X0+TX) x [Y0, Y0+TY) of its z segment and the matching
-// nodes. Iteration k:
+// nodes (TX = 32, TY = CH - 3; halo one column below and two above, the last
+// column of the 36 unused). Iteration k:
 //   P1  u of node plane k+1 into LDS (loaded one iteration earlier)
 //   P2  D and P* of cell plane k (halo 1): the divergence sums edge
 //       differences of u over the cell's two node planes; each node plane's
@@ -155,18 +174,18 @@ constexpr int remap_lds_doubles() {
 // Returns true if a tangled cell was seen (the predictor's volume).
 template <typename R, int CH>
 __device__ bool lagrange_tile(const RunArgs<R> &a, int b, double dtd, double *lds) {
-  constexpr int CW = 32, NTH = CW * CH, TX = CW - 3, TY = CH - 3;
+  constexpr int CW = kTileW, NTH = tile_threads<CH>(), TX = kTileX, TY = CH - 3, CHL = CH + 1;
   const Mesh &m = a.m;
   const State<R> &cur = a.cur;
   int tx, ty, seg;
   tile_of(a.ga, b, tx, ty, seg);
-  const int ci = threadIdx.x % CW, cj = threadIdx.x / CW;
+  const int ci = threadIdx.x % CW, cj = threadIdx.x / CW;  // cj == CH: a spare thread
   const int gi = tx * TX + ci - 1, gj = ty * TY + cj - 1;
   const int Z0 = seg * a.ga.seglen;
   const bool lastseg = seg == a.ga.nseg - 1;
   const int Z1 = lastseg ? m.nz : Z0 + a.ga.seglen;  // cell planes [Z0, Z1)
   const int NZ1 = lastseg ? m.nz + 1 : Z1;           // node planes [Z0, NZ1)
-  const bool ncol = gi >= 0 && gi <= m.nx && gj >= 0 && gj <= m.ny;
+  const bool ncol = cj < CH && gi >= 0 && gi <= m.nx && gj >= 0 && gj <= m.ny;
   const bool inner = ci < CW - 1 && cj < CH - 1;  // has the +x and +y neighbour column
   const bool ccol = inner && gi >= 0 && gi < m.nx && gj >= 0 && gj < m.ny;
   const bool nodecol = ci >= 1 && cj >= 1 && inner;  // u' computed here
@@ -176,12 +195,13 @@ __device__ bool lagrange_tile(const RunArgs<R> &a, int b, double dtd, double *ld
   const uint32_t cix = ccol ? (uint32_t)(gi + m.nx * gj) : 0u, nix = ncol ? (uint32_t)(gi + (m.nx + 1) * gj) : 0u;
 
   // LDS: bulk planes as R, delta ring as double
-  R(*sU)[CH][CW] = reinterpret_cast<R(*)[CH][CW]>(lds);                // [3]
-  R(*sP)[CW] = reinterpret_cast<R(*)[CW]>(lds + 3 * CH * CW);          // P*
-  R(*sM)[CW] = reinterpret_cast<R(*)[CW]>(lds + 4 * CH * CW);          // m
-  double(*sD)[3][CH][CW] = reinterpret_cast<double(*)[3][CH][CW]>(lds + 5 * CH * CW);  // [2][3]
+  R(*sU)[CHL][CW] = reinterpret_cast<R(*)[CHL][CW]>(lds);                 // [3]
+  R(*sP)[CW] = reinterpret_cast<R(*)[CW]>(lds + 3 * CHL * CW);            // P*
+  R(*sM)[CW] = reinterpret_cast<R(*)[CW]>(lds + 4 * CHL * CW);            // m
+  double(*sD)[3][CHL][CW] = reinterpret_cast<double(*)[3][CHL][CW]>(lds + 5 * CHL * CW);  // [2][3]
+  static_assert(11 * CHL * CW <= lagrange_lds_doubles<CH>(), "lagrange LDS layout");
 
-  for (int q = threadIdx.x; q < 2 * 3 * CH * CW; q += NTH) (&sD[0][0][0][0])[q] = 0.0;
+  for (int q = threadIdx.x; q < 2 * 3 * CHL * CW; q += NTH) (&sD[0][0][0][0])[q] = 0.0;
 
   const R dt = R(dtd);
   const R ax = R(m.ax), ay = R(m.ay), az = R(m.az), V0 = R(m.V0);
@@ -289,8 +309,8 @@ __device__ bool lagrange_tile(const RunArgs<R> &a, int b, double dtd, double *ld
     const int cp = k - 1;
     const bool plane_ok = cp >= 0 && cp < m.nz && k > Z0 - 2;
     {
-      const double(*A)[CH][CW] = sD[cp & 1];  // node plane k-1
-      const double(*B)[CH][CW] = sD[k & 1];   // node plane k
+      const double(*A)[CHL][CW] = sD[cp & 1];  // node plane k-1
+      const double(*B)[CHL][CW] = sD[k & 1];   // node plane k
       double qxd = 0.0, qyd = 0.0, qzd = 0.0;
       if (inner) {
         qxd = (B[0][cj][ci + 1] - B[0][cj][ci]) + (B[0][cj + 1][ci + 1] - B[0][cj + 1][ci]);
@@ -351,7 +371,7 @@ __device__ bool lagrange_tile(const RunArgs<R> &a, int b, double dtd, double *ld
 // ---------------------------------------------------------------------------------
 // Column (ci, cj) is node column / cell column (X0 + ci - 2, Y0 + cj - 2). The
 // tile owns cells [X0, X0+TX) x [Y0, Y0+TY) of its z segment and the matching
-// nodes. Iteration c:
+// nodes (TX = 32, TY = CH - 4; halo two columns on each side). Iteration c:
 //   P1  Lagrangian results of cell plane c+1 (halo 2 below, 1 above) and u'
 //       of node plane c+1 into LDS (loaded one iteration earlier)
 //   P2  donor-cell fluxes of the cell's lower and upper x/y faces (a face's
@@ -369,7 +389,8 @@ __device__ bool lagrange_tile(const RunArgs<R> &a, int b, double dtd, double *ld
 template <typename R, int CH>
 __device__ void remap_tile(const RunArgs<R> &a, int b, double *lds, double *amax_out, bool *bad_out,
                            bool *tangle_out) {
-  constexpr int CW = 32, NTH = CW * CH, TX = CW - 4, TY = CH - 4;
+  constexpr int CW = kTileW, NTH = tile_threads<CH>(), TX = kTileX, TY = CH - 4, CHL = CH + 1;
+  static_assert(TX == CW - 4, "remap halo");
   const Mesh &m = a.m;
   int tx, ty, seg;
   tile_of(a.gb, b, tx, ty, seg);
@@ -380,11 +401,11 @@ __device__ void remap_tile(const RunArgs<R> &a, int b, double *lds, double *amax
   const int Z1 = lastseg ? m.nz : Z0 + a.gb.seglen;  // cell planes [Z0, Z1)
   const int NZ1 = lastseg ? m.nz + 1 : Z1;           // node planes [Z0, NZ1)
   const bool own_cell = ci >= 2 && cj >= 2 && ci < 2 + TX && cj < 2 + TY && gi < m.nx && gj < m.ny;
-  const bool own_node = ci >= 2 && cj >= 2 && gi <= m.nx && gj <= m.ny && (ci < 2 + TX || gi == m.nx) &&
+  const bool own_node = ci >= 2 && cj >= 2 && cj < CH && gi <= m.nx && gj <= m.ny && (ci < 2 + TX || gi == m.nx) &&
                         (cj < 2 + TY || gj == m.ny);
 
   // LDS: the x/y swept volumes of plane c+1 as double, then planes of R
-  // (32 x CH values each) reused across phases. P1 of the next plane writes
+  // (CW x (CH + 1) values each) reused across phases. P1 of the next plane writes
   // only RL, EL, the swept volumes and the u' ring, which P6 does not read,
   // so no barrier separates P6 from it; P2, which writes R planes 2..6, comes
   // after P1's barrier.
@@ -396,15 +417,15 @@ __device__ void remap_tile(const RunArgs<R> &a, int b, double *lds, double *amax
     NSLOT = 7
   };
   double(*sVX)[CW] = reinterpret_cast<double(*)[CW]>(lds);
-  double(*sVY)[CW] = reinterpret_cast<double(*)[CW]>(lds + CH * CW);
-  R *const rbase = reinterpret_cast<R *>(lds + 2 * CH * CW);
-  auto RS = [&](int s) { return reinterpret_cast<R(*)[CW]>(rbase + s * CH * CW); };
-  R(*UPR)[3][CH][CW] = reinterpret_cast<R(*)[3][CH][CW]>(rbase + NSLOT * CH * CW);  // [3][3]
-  static_assert(2 * CH * CW * 8 + (NSLOT + 9) * CH * CW * (int)sizeof(R) <= remap_lds_doubles<R, CH>() * 8,
+  double(*sVY)[CW] = reinterpret_cast<double(*)[CW]>(lds + CHL * CW);
+  R *const rbase = reinterpret_cast<R *>(lds + 2 * CHL * CW);
+  auto RS = [&](int s) { return reinterpret_cast<R(*)[CW]>(rbase + s * CHL * CW); };
+  R(*UPR)[3][CHL][CW] = reinterpret_cast<R(*)[3][CHL][CW]>(rbase + NSLOT * CHL * CW);  // [3][3]
+  static_assert(2 * CHL * CW * 8 + (NSLOT + 9) * CHL * CW * (int)sizeof(R) <= remap_lds_doubles<R, CH>() * 8,
                 "remap LDS layout");
 
-  const bool ccol = gi >= 0 && gi < m.nx && gj >= 0 && gj < m.ny;
-  const bool ncol = gi >= 0 && gi <= m.nx && gj >= 0 && gj <= m.ny;
+  const bool ccol = cj < CH && gi >= 0 && gi < m.nx && gj >= 0 && gj < m.ny;
+  const bool ncol = cj < CH && gi >= 0 && gi <= m.nx && gj >= 0 && gj <= m.ny;
   const int64_t cpl = (int64_t)m.nx * m.ny, npl = (int64_t)(m.nx + 1) * (m.ny + 1);
   const uint32_t cix = ccol ? (uint32_t)(gi + m.nx * gj) : 0u, nix = ncol ? (uint32_t)(gi + (m.nx + 1) * gj) : 0u;
   const bool r1 = ci >= 1 && cj >= 1 && ci <= CW - 2 && cj <= CH - 2;  // cells and nodes [-1, T]
@@ -718,7 +739,7 @@ __device__ void remap_tile(const RunArgs<R> &a, int b, double *lds, double *amax
 // No-op step of a tile: carry the owned part of the state into the other buffer.
 template <typename R, int CH>
 __device__ void copy_tile(const RunArgs<R> &a, int b) {
-  constexpr int CW = 32, TX = CW - 4, TY = CH - 4;
+  constexpr int CW = kTileW, TX = kTileX, TY = CH - 4;
   const Mesh &m = a.m;
   int tx, ty, seg;
   tile_of(a.gb, b, tx, ty, seg);
@@ -729,7 +750,7 @@ __device__ void copy_tile(const RunArgs<R> &a, int b) {
   const int Z1 = lastseg ? m.nz : Z0 + a.gb.seglen;
   const int NZ1 = lastseg ? m.nz + 1 : Z1;
   const bool own_cell = ci >= 2 && cj >= 2 && ci < 2 + TX && cj < 2 + TY && gi < m.nx && gj < m.ny;
-  const bool own_node = ci >= 2 && cj >= 2 && gi <= m.nx && gj <= m.ny && (ci < 2 + TX || gi == m.nx) &&
+  const bool own_node = ci >= 2 && cj >= 2 && cj < CH && gi <= m.nx && gj <= m.ny && (ci < 2 + TX || gi == m.nx) &&
                         (cj < 2 + TY || gj == m.ny);
   for (int c = Z0; c < Z1; c++)
     if (own_cell) {

@@ -353,7 +353,7 @@ class SaleRun:
             raise SaleError(rc, "sale_step_timed")
         return ms
 
-    def set_launch(self, rows_lagrange=16, rows_remap=16, target_blocks=0):
+    def set_launch(self, rows_lagrange=14, rows_remap=14, target_blocks=0):
         rc = sale_set_launch(self.ctx, rows_lagrange, rows_remap, target_blocks)
         if rc != SALE_OK:
             raise SaleError(rc, "sale_set_launch")

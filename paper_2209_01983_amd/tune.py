@@ -1,7 +1,7 @@
 """Autotuner of the step kernels' launch shape.
 
-The two z-marching step kernels take a tile shape (32 x rows columns, rows 8,
-16 or 32, chosen per kernel) and a target block count for the split of the z
+The two z-marching step kernels take a tile shape (36 x rows columns, rows 7,
+14 or 28, chosen per kernel) and a target block count for the split of the z
 extent into segments. Results do not depend on the shape; speed does, per
 mesh size and precision. `tune` times every candidate with the library's
 per-kernel event timing on a live run and keeps the fastest; results are
@@ -18,7 +18,7 @@ import os
 
 from . import sale
 
-ROWS = (8, 16, 32)
+ROWS = (7, 14, 28)
 TARGETS = (0, 1024, 2048, 3072, 6144, 12288)  # 0: the library's automatic split
 KERNELS = ("lagrange", "remap")
 
@@ -98,15 +98,15 @@ def tune(cfg, prob=None, steps=6, warmup=2, rows=ROWS, targets=TARGETS, path=Non
     order2 = cfg.remap_order == 2
     for t in targets:
         for r in rows:
-            # (order 2: the remap passes ignore the remap rows; keep them at 16)
-            run.set_launch(r, 16 if order2 else r, t)
+            # (order 2: the remap passes ignore the remap rows; keep them at 14)
+            run.set_launch(r, 14 if order2 else r, t)
             run.step(warmup)
             ms = run.step_timed(steps)
             times[(r, t)] = (ms[1] / steps, ms[2] / steps)
     run.close()
     best = choose(times)
     if order2:
-        best["rows_b"] = 16
+        best["rows_b"] = 14
     if save:
         cache = load_cache(path)
         a = arch()
