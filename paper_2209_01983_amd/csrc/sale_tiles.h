@@ -125,33 +125,37 @@ __device__ __forceinline__ void tile_of(const Grid2 &g, int b, int &tx, int &ty,
   seg = r / g.ty;
 }
 
-// Tile geometry. A tile is kTileW = 36 columns in x by CH rows in y, of which
-// the middle kTileX = 32 in x are owned: a row of a tile's owned cells is a
-// whole number of 128-byte lines (32 doubles or floats, on meshes whose x
-// extent is a multiple of 16 cells), so neighbouring tiles never write parts
-// of the same line (a line written in parts by two blocks costs the memory
-// system far more than whole lines) and 320 cells split into 10 tiles. The
-// block rounds the 36 x CH threads up to a multiple of 64; the spare threads
-// map to an LDS row CH of their own and own nothing, so every wave is whole
-// and every thread meets every barrier.
-constexpr int kTileW = 36, kTileX = 32;
+// Tile geometry. A tile is CW columns in x by CH rows in y, of which
+// kTileX = 32 in x are owned: a row of a tile's owned cells is a whole number
+// of 128-byte lines (32 doubles or floats, on meshes whose x extent is a
+// multiple of 16 cells), so neighbouring tiles never write parts of the same
+// line (a line written in parts by two blocks costs the memory system far
+// more than whole lines) and 320 cells split into 10 tiles. The halo makes
+// the Lagrange tile kTileWL = 35 columns wide (one below, two above) and the
+// remap tile kTileW = 36 (two on each side). A block rounds 36 x CH threads
+// up to a multiple of 64; the spare threads map to LDS rows CH and beyond of
+// their own and own nothing, so every wave is whole and every thread meets
+// every barrier.
+constexpr int kTileW = 36, kTileWL = 35, kTileX = 32;
 template <int CH>
 constexpr int tile_threads() {
   return (kTileW * CH + 63) / 64 * 64;
 }
-static_assert(tile_threads<7>() - kTileW * 7 < kTileW && tile_threads<14>() - kTileW * 14 < kTileW &&
-                  tile_threads<28>() - kTileW * 28 < kTileW,
-              "the spare threads of a block fit in one LDS row");
+// rows of an LDS plane of a CW-wide tile: CH and the spare threads' rows
+template <int CW, int CH>
+constexpr int lds_rows() {
+  return (tile_threads<CH>() + CW - 1) / CW;
+}
 
-// LDS doubles needed by each tile function (planes of kTileW x (CH + 1))
+// LDS doubles needed by each tile function (planes of CW x lds_rows)
 template <int CH>
 constexpr int lagrange_lds_doubles() {
-  return 11 * kTileW * (CH + 1);
+  return 11 * kTileWL * lds_rows<kTileWL, CH>();
 }
 // (remap: two double planes, then 16 planes of the bulk type R)
 template <typename R, int CH>
 constexpr int remap_lds_doubles() {
-  return (2 * 8 + 16 * (int)sizeof(R)) * kTileW * (CH + 1) / 8;
+  return (2 * 8 + 16 * (int)sizeof(R)) * kTileW * lds_rows<kTileW, CH>() / 8;
 }
 
 // ---------------------------------------------------------------------------------
@@ -159,8 +163,8 @@ constexpr int remap_lds_doubles() {
 // ---------------------------------------------------------------------------------
 // Column (ci, cj) is node column / cell column (X0 + ci - 1, Y0 + cj - 1). The
 // tile owns cells [X0, X0+TX) x [Y0, Y0+TY) of its z segment and the matching
-// nodes (TX = 32, TY = CH - 3; halo one column below and two above, the last
-// column of the 36 unused). Iteration k:
+// nodes (TX = 32, TY = CH - 3; halo one column below and two above).
+// Iteration k:
 //   P1  u of node plane k+1 into LDS (loaded one iteration earlier)
 //   P2  D and P* of cell plane k (halo 1): the divergence sums edge
 //       differences of u over the cell's two node planes; each node plane's
@@ -174,7 +178,8 @@ constexpr int remap_lds_doubles() {
 // Returns true if a tangled cell was seen (the predictor's volume).
 template <typename R, int CH>
 __device__ bool lagrange_tile(const RunArgs<R> &a, int b, double dtd, double *lds) {
-  constexpr int CW = kTileW, NTH = tile_threads<CH>(), TX = kTileX, TY = CH - 3, CHL = CH + 1;
+  constexpr int CW = kTileWL, NTH = tile_threads<CH>(), TX = kTileX, TY = CH - 3, CHL = lds_rows<CW, CH>();
+  static_assert(TX == CW - 3, "lagrange halo");
   const Mesh &m = a.m;
   const State<R> &cur = a.cur;
   int tx, ty, seg;
@@ -389,7 +394,7 @@ __device__ bool lagrange_tile(const RunArgs<R> &a, int b, double dtd, double *ld
 template <typename R, int CH>
 __device__ void remap_tile(const RunArgs<R> &a, int b, double *lds, double *amax_out, bool *bad_out,
                            bool *tangle_out) {
-  constexpr int CW = kTileW, NTH = tile_threads<CH>(), TX = kTileX, TY = CH - 4, CHL = CH + 1;
+  constexpr int CW = kTileW, NTH = tile_threads<CH>(), TX = kTileX, TY = CH - 4, CHL = lds_rows<CW, CH>();
   static_assert(TX == CW - 4, "remap halo");
   const Mesh &m = a.m;
   int tx, ty, seg;
@@ -465,7 +470,9 @@ __device__ void remap_tile(const RunArgs<R> &a, int b, double *lds, double *amax
       if (cp + 1 < m.nz) f_vzu = plane_at<const R>(a.geo.dvz, cpl, cp + 1, oR);
       f_rho = plane_at<const R>(a.cur.rho, cpl, cp, oR);
     }
-    if (ncol && cp >= 0 && cp <= m.nz) {
+    // (u' is read by the momentum remap of nodes [2, CW-2] x [2, CH-2] from
+    // their neighbours: column 0 and row 0 are never read)
+    if (ncol && ci >= 1 && cj >= 1 && cp >= 0 && cp <= m.nz) {
       const uint32_t o = nix * (uint32_t)sizeof(R);
       f_u = plane_at<const R>(a.up, npl, cp, o);
       f_v = plane_at<const R>(a.vp, npl, cp, o);
