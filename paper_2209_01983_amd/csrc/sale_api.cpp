@@ -649,8 +649,8 @@ sale::PoolRun<R> pool_image(const PoolSlot &sl, const Work<R> &w) {
   r.wp = w.wp;
   r.geo = w.geo;
   // one z segment per tile: the pool's parallelism comes from its many runs
-  r.ga = sale::grid_lagrange(sl.m, 1, sale::kPoolRows);
-  r.gb = sale::grid_remap(sl.m, 1, sale::kPoolRows);
+  r.ga = sale::grid_lagrange(sl.m, 1, sale::kPoolRows, sale::kPoolWidth);
+  r.gb = sale::grid_remap(sl.m, 1, sale::kPoolRows, sale::kPoolWidth);
   r.step0 = sl.step0;
   r.step_target = sl.step_target;
   return r;
@@ -795,8 +795,8 @@ int sale_pool_advance(sale_pool *p, int32_t max_steps_per_run) {
     for (int k : p->h_act) {
       PoolSlot &sl = p->slots[k];
       const int quota = (int)std::max(1.0, kLockBlocks * (double)sl.m.ncell / cells);
-      const sale::Grid2 ga = sale::grid_lagrange(sl.m, quota, sale::kPoolRows);
-      const sale::Grid2 gb = sale::grid_remap(sl.m, quota, sale::kPoolRows);
+      const sale::Grid2 ga = sale::grid_lagrange(sl.m, quota, sale::kPoolRows, sale::kPoolWidth);
+      const sale::Grid2 gb = sale::grid_remap(sl.m, quota, sale::kPoolRows, sale::kPoolWidth);
       hipError_t ce;
       if (p->precision == SALE_FP64) {
         sl.r64.ga = ga, sl.r64.gb = gb;

@@ -156,8 +156,9 @@ struct Launch {
 };
 bool launch_valid(const Launch &L);
 
-Grid2 grid_lagrange(const Mesh &m, int target_blocks, int rows);
-Grid2 grid_remap(const Mesh &m, int target_blocks, int rows);
+// (width: the tile's columns in x, halo included)
+Grid2 grid_lagrange(const Mesh &m, int target_blocks, int rows, int width);
+Grid2 grid_remap(const Mesh &m, int target_blocks, int rows, int width);
 constexpr int kStepThreads = 512;  // block size of the 16-row tiles (and of the pool kernel)
 
 template <typename R>
@@ -234,11 +235,12 @@ struct PoolQueue {
   unsigned int abort;       // set by a timed-out wait: later waits give up at once
 };
 
-// Tile rows of the multi-run kernels (their tiles are 36 x kPoolRows columns).
+// Tile shape of the multi-run kernels: kPoolWidth x kPoolRows columns (their
+// meshes are small: narrower tiles than the single-run kernels').
 #ifndef SALE_POOL_ROWS
-#define SALE_POOL_ROWS 14
+#define SALE_POOL_ROWS 16
 #endif
-constexpr int kPoolRows = SALE_POOL_ROWS;
+constexpr int kPoolRows = SALE_POOL_ROWS, kPoolWidth = 32;
 
 // Persistent multi-run advance: prepare (queue head, per-run counters, first
 // dt) and the persistent kernel over `blocks` blocks; tables on the device.

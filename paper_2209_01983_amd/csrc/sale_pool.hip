@@ -34,18 +34,18 @@ namespace sale {
 
 namespace {
 
-constexpr int CH = kPoolRows;
-// register cap of the lockstep tile kernels: that of the single-run kernels
-// of the same tile rows (4 waves per SIMD)
+constexpr int CH = kPoolRows, CW = kPoolWidth;
+// register cap of the lockstep tile kernels (4 waves per SIMD)
 constexpr int waves_of_lock() { return 4; }
-// the FP32 bulk remap tile of 14 rows fits 80 VGPRs and 42 KB of LDS: three
+// the FP32 bulk remap tile of 16 rows fits 80 VGPRs and 40 KB of LDS: three
 // blocks per CU
 template <typename R>
-constexpr int waves_of_lock_remap() { return sizeof(R) == 4 && CH == 14 ? 6 : waves_of_lock(); }
-constexpr int NT = tile_threads<CH>();
-constexpr int LDS_DOUBLES =
-    lagrange_lds_doubles<CH>() > remap_lds_doubles<double, CH>() ? lagrange_lds_doubles<CH>()
-                                                                 : remap_lds_doubles<double, CH>();
+constexpr int waves_of_lock_remap() { return sizeof(R) == 4 && CH == 16 ? 6 : waves_of_lock(); }
+constexpr int NT = tile_threads<CH, CW>();
+constexpr int LDS_L = lagrange_lds_doubles<CH, CW, NT>();
+template <typename R>
+constexpr int LDS_R = remap_lds_doubles<R, CH, CW, NT>();
+constexpr int LDS_DOUBLES = LDS_L > LDS_R<double> ? LDS_L : LDS_R<double>;
 // Cap of one wait, in ticks of the 100 MHz constant clock. A wait normally
 // lasts at most one tile of the same run (milliseconds).
 constexpr long long kWaitTicks = 200000000ll;  // 2 s
@@ -152,12 +152,12 @@ __global__ __launch_bounds__(NT, SALE_WAVES_POOL) void k_pool(const PoolRun<R> *
     if (ran) {
       const RunArgs<R> a = args_of(p);
       if (!remap) {
-        const bool t = lagrange_tile<R, CH>(a, tile, ctl->dt, lds);
+        const bool t = lagrange_tile<R, CH, CW, NT>(a, tile, ctl->dt, lds);
         if (t) atomicOr(&ctl->status, SALE_FLAG_TANGLE);
       } else {
         double amax;
         bool bad, tangle;
-        remap_tile<R, CH>(a, tile, lds, &amax, &bad, &tangle);
+        remap_tile<R, CH, CW, NT>(a, tile, lds, &amax, &bad, &tangle);
         block_max_to_ctl<NT>(ctl, amax, bad);
         if (tangle) atomicOr(&ctl->status, SALE_FLAG_TANGLE);
       }
@@ -206,21 +206,21 @@ template <typename R>
 __global__ __launch_bounds__(NT, waves_of_lock()) void k_lock_lagrange(const PoolRun<R> *__restrict__ runs,
                                                                       const int *__restrict__ act,
                                                                       const int *__restrict__ prefA, int nact) {
-  __shared__ double lds[lagrange_lds_doubles<CH>()];
+  __shared__ double lds[LDS_L];
   const int g = xcd_logical_block(blockIdx.x, gridDim.x);
   const int q = find_run(prefA, nact, g);
   const PoolRun<R> &p = runs[act[q]];
   Ctl *ctl = p.ctl;
   if (ctl->done) return;
   const RunArgs<R> a = args_of(p);
-  if (lagrange_tile<R, CH>(a, g - prefA[q], ctl->dt, lds)) atomicOr(&ctl->status, SALE_FLAG_TANGLE);
+  if (lagrange_tile<R, CH, CW, NT>(a, g - prefA[q], ctl->dt, lds)) atomicOr(&ctl->status, SALE_FLAG_TANGLE);
 }
 
 template <typename R>
 __global__ __launch_bounds__(NT, waves_of_lock_remap<R>()) void k_lock_remap(const PoolRun<R> *__restrict__ runs,
                                                                             const int *__restrict__ act,
                                                                             const int *__restrict__ prefB, int nact) {
-  __shared__ double lds[remap_lds_doubles<R, CH>()];
+  __shared__ double lds[LDS_R<R>];
   const int g = xcd_logical_block(blockIdx.x, gridDim.x);
   const int q = find_run(prefB, nact, g);
   const PoolRun<R> &p = runs[act[q]];
@@ -229,7 +229,7 @@ __global__ __launch_bounds__(NT, waves_of_lock_remap<R>()) void k_lock_remap(con
   const RunArgs<R> a = args_of(p);
   double amax;
   bool bad, tangle;
-  remap_tile<R, CH>(a, g - prefB[q], lds, &amax, &bad, &tangle);
+  remap_tile<R, CH, CW, NT>(a, g - prefB[q], lds, &amax, &bad, &tangle);
   block_max_to_ctl<NT>(ctl, amax, bad);
   if (tangle) atomicOr(&ctl->status, SALE_FLAG_TANGLE);
 }

@@ -377,11 +377,11 @@ static int resident_blocks(int rows) {
     default: return 256;
   }
 }
-Grid2 grid_lagrange(const Mesh &m, int target_blocks, int rows) {
-  return make_grid(m.nx, m.ny, m.nz, kTileX, rows - 3, target_blocks, 3, resident_blocks(rows));
+Grid2 grid_lagrange(const Mesh &m, int target_blocks, int rows, int width) {
+  return make_grid(m.nx, m.ny, m.nz, width - 3, rows - 3, target_blocks, 3, resident_blocks(rows));
 }
-Grid2 grid_remap(const Mesh &m, int target_blocks, int rows) {
-  return make_grid(m.nx, m.ny, m.nz, kTileX, rows - 4, target_blocks, 4, resident_blocks(rows));
+Grid2 grid_remap(const Mesh &m, int target_blocks, int rows, int width) {
+  return make_grid(m.nx, m.ny, m.nz, width - 4, rows - 4, target_blocks, 4, resident_blocks(rows));
 }
 
 bool launch_valid(const Launch &L) {
@@ -445,10 +445,10 @@ void layout_split(const Mesh &m, void *state, void *inter, Ctl **ctl, Work<R> *w
     w->s[a].w = takeR(nR);
   }
   p = (char *)inter;
+  w->geo.rl = nullptr;
   w->up = takeR(nR);
   w->vp = takeR(nR);
   w->wp = takeR(nR);
-  w->geo.rl = nullptr;
   w->geo.el = takeR(cR);
   w->geo.dvx = takeR(cR);
   w->geo.dvy = takeR(cR);
@@ -550,8 +550,8 @@ RunArgs<R> run_args(const Mesh &m, Ctl *ctl, const Work<R> &w, int cur, const La
   a.vp = w.vp;
   a.wp = w.wp;
   a.geo = w.geo;
-  a.ga = grid_lagrange(m, L.target, L.rows_a);
-  a.gb = grid_remap(m, L.target, L.rows_b);
+  a.ga = grid_lagrange(m, L.target, L.rows_a, kTileWL);
+  a.gb = grid_remap(m, L.target, L.rows_b, kTileW);
   return a;
 }
 

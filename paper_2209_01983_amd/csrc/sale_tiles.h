@@ -133,29 +133,33 @@ __device__ __forceinline__ void tile_of(const Grid2 &g, int b, int &tx, int &ty,
 // more than whole lines) and 320 cells split into 10 tiles. The halo makes
 // the Lagrange tile kTileWL = 35 columns wide (one below, two above) and the
 // remap tile kTileW = 36 (two on each side). A block rounds 36 x CH threads
-// up to a multiple of 64; the spare threads map to LDS rows CH and beyond of
-// their own and own nothing, so every wave is whole and every thread meets
-// every barrier.
+// up to a multiple of 64 (tile_threads); the spare threads map to LDS rows CH
+// and beyond of their own and own nothing, so every wave is whole and every
+// thread meets every barrier. The tile width is a template parameter: the
+// multi-run kernels, whose meshes are 16-64 cells across, keep tiles 32
+// columns wide (29 and 28 owned), which waste less of a small mesh.
 constexpr int kTileW = 36, kTileWL = 35, kTileX = 32;
-template <int CH>
+template <int CH, int CW = kTileW>
 constexpr int tile_threads() {
-  return (kTileW * CH + 63) / 64 * 64;
+  return (CW * CH + 63) / 64 * 64;
 }
-// rows of an LDS plane of a CW-wide tile: CH and the spare threads' rows
-template <int CW, int CH>
+// rows of an LDS plane of a CW-wide tile in a block of NT threads: CH and the
+// spare threads' rows
+template <int CW, int CH, int NT>
 constexpr int lds_rows() {
-  return (tile_threads<CH>() + CW - 1) / CW;
+  return (NT + CW - 1) / CW;
 }
 
-// LDS doubles needed by each tile function (planes of CW x lds_rows)
-template <int CH>
+// LDS doubles needed by each tile function (planes of CW x lds_rows) in a
+// block of NT threads
+template <int CH, int CW = kTileWL, int NT = tile_threads<CH>()>
 constexpr int lagrange_lds_doubles() {
-  return 11 * kTileWL * lds_rows<kTileWL, CH>();
+  return 11 * CW * lds_rows<CW, CH, NT>();
 }
 // (remap: two double planes, then 16 planes of the bulk type R)
-template <typename R, int CH>
+template <typename R, int CH, int CW = kTileW, int NT = tile_threads<CH>()>
 constexpr int remap_lds_doubles() {
-  return (2 * 8 + 16 * (int)sizeof(R)) * kTileW * lds_rows<kTileW, CH>() / 8;
+  return (2 * 8 + 16 * (int)sizeof(R)) * CW * lds_rows<CW, CH, NT>() / 8;
 }
 
 // ---------------------------------------------------------------------------------
@@ -175,11 +179,12 @@ constexpr int remap_lds_doubles() {
 //       delta on node planes k-1 and k only), its compatible-energy work and
 //       e^L; hand-off to remap_tile, which forms V^L and rho^L from the six
 //       faces' swept volumes
-// Returns true if a tangled cell was seen (the predictor's volume).
-template <typename R, int CH>
+// Returns true if a tangled cell was seen (the predictor's volume). CW: tile
+// width, NTH: block size.
+template <typename R, int CH, int CW = kTileWL, int NTH = tile_threads<CH>()>
 __device__ bool lagrange_tile(const RunArgs<R> &a, int b, double dtd, double *lds) {
-  constexpr int CW = kTileWL, NTH = tile_threads<CH>(), TX = kTileX, TY = CH - 3, CHL = lds_rows<CW, CH>();
-  static_assert(TX == CW - 3, "lagrange halo");
+  constexpr int TX = CW - 3, TY = CH - 3, CHL = lds_rows<CW, CH, NTH>();
+  static_assert(CW * CH <= NTH, "one thread per column");
   const Mesh &m = a.m;
   const State<R> &cur = a.cur;
   int tx, ty, seg;
@@ -204,7 +209,7 @@ __device__ bool lagrange_tile(const RunArgs<R> &a, int b, double dtd, double *ld
   R(*sP)[CW] = reinterpret_cast<R(*)[CW]>(lds + 3 * CHL * CW);            // P*
   R(*sM)[CW] = reinterpret_cast<R(*)[CW]>(lds + 4 * CHL * CW);            // m
   double(*sD)[3][CHL][CW] = reinterpret_cast<double(*)[3][CHL][CW]>(lds + 5 * CHL * CW);  // [2][3]
-  static_assert(11 * CHL * CW <= lagrange_lds_doubles<CH>(), "lagrange LDS layout");
+  static_assert(11 * CHL * CW <= lagrange_lds_doubles<CH, CW, NTH>(), "lagrange LDS layout");
 
   for (int q = threadIdx.x; q < 2 * 3 * CHL * CW; q += NTH) (&sD[0][0][0][0])[q] = 0.0;
 
@@ -391,11 +396,11 @@ __device__ bool lagrange_tile(const RunArgs<R> &a, int b, double dtd, double *ld
 // u' is kept in a 3-plane LDS ring (node planes c-1, c, c+1).
 // Writes the new state; returns the tile's largest signal speed in *amax and
 // whether an owned cell or node was inadmissible in *bad.
-template <typename R, int CH>
+template <typename R, int CH, int CW = kTileW, int NTH = tile_threads<CH>()>
 __device__ void remap_tile(const RunArgs<R> &a, int b, double *lds, double *amax_out, bool *bad_out,
                            bool *tangle_out) {
-  constexpr int CW = kTileW, NTH = tile_threads<CH>(), TX = kTileX, TY = CH - 4, CHL = lds_rows<CW, CH>();
-  static_assert(TX == CW - 4, "remap halo");
+  constexpr int TX = CW - 4, TY = CH - 4, CHL = lds_rows<CW, CH, NTH>();
+  static_assert(CW * CH <= NTH, "one thread per column");
   const Mesh &m = a.m;
   int tx, ty, seg;
   tile_of(a.gb, b, tx, ty, seg);
@@ -426,7 +431,7 @@ __device__ void remap_tile(const RunArgs<R> &a, int b, double *lds, double *amax
   R *const rbase = reinterpret_cast<R *>(lds + 2 * CHL * CW);
   auto RS = [&](int s) { return reinterpret_cast<R(*)[CW]>(rbase + s * CHL * CW); };
   R(*UPR)[3][CHL][CW] = reinterpret_cast<R(*)[3][CHL][CW]>(rbase + NSLOT * CHL * CW);  // [3][3]
-  static_assert(2 * CHL * CW * 8 + (NSLOT + 9) * CHL * CW * (int)sizeof(R) <= remap_lds_doubles<R, CH>() * 8,
+  static_assert(2 * CHL * CW * 8 + (NSLOT + 9) * CHL * CW * (int)sizeof(R) <= remap_lds_doubles<R, CH, CW, NTH>() * 8,
                 "remap LDS layout");
 
   const bool ccol = cj < CH && gi >= 0 && gi < m.nx && gj >= 0 && gj < m.ny;
@@ -746,7 +751,7 @@ __device__ void remap_tile(const RunArgs<R> &a, int b, double *lds, double *amax
 // No-op step of a tile: carry the owned part of the state into the other buffer.
 template <typename R, int CH>
 __device__ void copy_tile(const RunArgs<R> &a, int b) {
-  constexpr int CW = kTileW, TX = kTileX, TY = CH - 4;
+  constexpr int CW = kTileW, TX = CW - 4, TY = CH - 4;
   const Mesh &m = a.m;
   int tx, ty, seg;
   tile_of(a.gb, b, tx, ty, seg);
