@@ -25,10 +25,13 @@ Also reported (one JSON line, extra keys):
   lagrange128  pure-Lagrangian mode (the mesh moves with the flow), Sedov
                128^3, FP64: per-step throughput over a 100-step window after
                10 warm-up steps, kernel split (forces+nodes, energy+geometry).
-  batched      256 runs (seeded mix of Sod / Sedov, edges 16..64), MIXED32,
-               200 steps each in ONE pool advance (lockstep launches): aggregate
-               cell-updates/s, makespan, per-run latency p50/p99; the same
-               runs one after another on the plain FP64 path.
+  batched      256 runs (seeded mix of Sod / Sedov, edges 16..64), MIXED32
+               and FP64, 200 steps each in ONE pool advance, in three advance
+               modes (one persistent launch; lockstep kernels with the steps
+               after the first replayed from a captured HIP graph; lockstep
+               kernels all launched): aggregate cell-updates/s, makespan,
+               per-run latency p50/p99; the same runs one after another on the
+               plain FP64 path.
   serving      seeded Poisson trace (50 requests/s, cubic 32^3..192^3,
                100..500 steps), continuous batching under an HBM budget, in
                MIXED32 and FP64: throughput and arrival -> result latency.
@@ -75,6 +78,11 @@ def parse():
                          "(default: 128 in the full run, none with --quick; 0: none)")
     ap.add_argument("--section", default="", choices=("", "latency", "sedov128", "noh128", "lagrange128", "batched", "serving"),
                     help="run only this extra block and print its JSON (for profiling it)")
+    ap.add_argument("--pool-modes", default=",".join(m for m, _ in POOL_MODES),
+                    help="batched block: the pool advance modes to run (comma list)")
+    ap.add_argument("--batched-steps", type=int, default=200, help="batched block: steps per run")
+    ap.add_argument("--no-seq", action="store_true",
+                    help="batched block: skip the sequential single-run FP64 comparison")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run one plain device copy of 2 GiB (reference for HBM counters)")
     return ap.parse_args()
@@ -265,34 +273,44 @@ def lagrange128(steps=100, warmup=10):
             "sim_time_end_of_window": t}
 
 
-def _with_pool_mode(persistent, fn):
-    """Run fn() with pools created in the persistent-kernel advance mode (the
-    library reads SALE_POOL_PERSISTENT when a pool is created) or in the
-    default lockstep mode."""
-    old = os.environ.get("SALE_POOL_PERSISTENT")
-    os.environ["SALE_POOL_PERSISTENT"] = "1" if persistent else "0"
+def _with_pool_mode(env, fn):
+    """Run fn() with pools created under the environment settings `env`
+    (the library reads SALE_POOL_PERSISTENT and SALE_POOL_GRAPHS when a pool
+    is created)."""
+    old = {k: os.environ.get(k) for k in env}
+    os.environ.update(env)
     try:
         return fn()
     finally:
-        if old is None:
-            del os.environ["SALE_POOL_PERSISTENT"]
-        else:
-            os.environ["SALE_POOL_PERSISTENT"] = old
+        for k, v in old.items():
+            if v is None:
+                del os.environ[k]
+            else:
+                os.environ[k] = v
 
 
-def batched(seq_fp64=True):
+POOL_MODES = (("persistent", {"SALE_POOL_PERSISTENT": "1"}),
+              ("lockstep", {"SALE_POOL_PERSISTENT": "0", "SALE_POOL_GRAPHS": "1"}),
+              ("lockstep_launched", {"SALE_POOL_PERSISTENT": "0", "SALE_POOL_GRAPHS": "0"}))
+
+
+def batched(seq_fp64=True, modes=None, steps=200):
     from paper_2209_01983_amd import sale, workloads
     from paper_2209_01983_amd.inputs import BATCH_SEED, batch_mix
 
     reqs = batch_mix(256, seed=BATCH_SEED)
-    steps = 200
-    out = {"workload": "256 runs, edges 16..64 (seed 2209), 128 sod + 128 sedov, 200 steps, one pool advance",
+    modes = [m for m, _ in POOL_MODES] if modes is None else modes
+    out = {"workload": f"256 runs, edges 16..64 (seed 2209), 128 sod + 128 sedov, {steps} steps, one pool advance",
            "cells_total": sum(workloads.cells(r) for r in reqs),
            "modes": {"persistent": "one launch of the persistent kernel per advance (work items pulled from a "
                                    "device queue, per-run phase waits)",
-                     "lockstep": "per step: one launch each for dt, the Lagrange tiles of all runs and the remap "
-                                 "tiles of all runs"}}
-    for mode, persistent in (("persistent", True), ("lockstep", False)):
+                     "lockstep": "per step: one kernel each for dt, the Lagrange tiles of all runs, the remap "
+                                 "tiles of all runs and the clocks; the first step launched, the other 199 "
+                                 "replays of one captured HIP graph of a step",
+                     "lockstep_launched": "the lockstep kernels, every step launched (no graph)"}}
+    for mode, env in POOL_MODES:
+        if mode not in modes:
+            continue
         def one(prec):
             r = workloads.run_batched(reqs, steps, prec)
             r["pool"].close()
@@ -305,9 +323,10 @@ def batched(seq_fp64=True):
             return {"mixed32": one(sale.SALE_MIXED32), "fp64": one(sale.SALE_FP64)}
 
         say("batched", mode)
-        out[mode] = _with_pool_mode(persistent, both)
+        out[mode] = _with_pool_mode(env, both)
     # the headline figures of the block: the persistent launch
-    out["mixed32"], out["fp64"] = out["persistent"]["mixed32"], out["persistent"]["fp64"]
+    if "persistent" in out:
+        out["mixed32"], out["fp64"] = out["persistent"]["mixed32"], out["persistent"]["fp64"]
     if seq_fp64:
         wall, cps, lat = workloads.run_sequential(reqs, steps, sale.SALE_FP64)
         out["fp64_sequential_plain"] = {"cell_updates_per_s": cps, "wall_s": wall,
@@ -486,7 +505,8 @@ def main():
 
     if a.section:
         block = {"latency": lambda: sod_latency(50), "sedov128": lambda: sedov128(3), "noh128": lambda: noh128(3),
-                 "lagrange128": lagrange128, "batched": batched,
+                 "lagrange128": lagrange128,
+                 "batched": lambda: batched(not a.no_seq, a.pool_modes.split(","), a.batched_steps),
                  "serving": lambda: serving(a.serve_requests, a.serve_budget_gb)}[a.section]
         print(json.dumps({a.section: block()}), flush=True)
         return

@@ -273,7 +273,11 @@ void sale_destroy(sale_ctx *ctx);
  * from a device queue, a run's phase waiting only for that run's previous
  * phase. Each run has its own time step; a run that is done skips its tiles.
  * A run's results do not depend on which other runs share the pool, nor on
- * the advance mode. */
+ * the advance mode. In the lockstep mode the rounds after an advance's first
+ * are replays of one HIP graph of a round's four launches, captured on a
+ * stream of the pool's own and kept while the set of active runs and the
+ * block counts stay the same (SALE_POOL_GRAPHS=0 at sale_pool_create
+ * launches every round instead); the graph holds kernel launches only. */
 typedef struct sale_pool sale_pool;
 
 /* Create a pool of up to max_runs slots over the device arena
@@ -297,9 +301,11 @@ int sale_pool_admit(sale_pool *pool, const sale_config *cfg, const sale_problem 
                     int32_t *slot);
 
 /* Advance every unfinished admitted run by up to max_steps_per_run steps:
- * lockstep rounds of launches, or one persistent launch. Synchronises the
- * stream first (the tables of the runs in the advance are copied from host
- * memory), then enqueues the advance and returns without waiting for it. */
+ * lockstep rounds (the first launched, the rest graph replays), or one
+ * persistent launch. Synchronises the stream first (the tables of the runs
+ * in the advance are copied from host memory), then enqueues the advance and
+ * returns without waiting for it. A failed capture or instantiation of the
+ * round graph returns SALE_EHIP after the first round was enqueued. */
 int sale_pool_advance(sale_pool *pool, int32_t max_steps_per_run);
 
 /* Synchronise the stream and list, in done[0..*n_done), the slots whose run

@@ -602,6 +602,18 @@ struct sale_pool {
   sale::PoolQueue h_q;
   int resident;
   bool lockstep;  // advance by lockstep launches (default) or by the persistent kernel
+  // Lockstep rounds after an advance's first are replays of one captured
+  // graph of a round (its four launches), kept while the round's shape --
+  // active runs and block counts -- stays the same. SALE_POOL_GRAPHS=0 at
+  // creation launches every round instead.
+  bool graphs = true;
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t round_graph = nullptr;
+  int g_nact = -1, g_totA = -1, g_totB = -1;
+  ~sale_pool() {
+    if (round_graph) (void)hipGraphExecDestroy(round_graph);
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
+  }
 };
 
 namespace sale_host {
@@ -703,6 +715,8 @@ int sale_pool_create(int32_t precision, int32_t max_runs, void *d_arena, size_t 
   // per advance, device-side phase waits) instead of lockstep launches
   const char *pers = getenv("SALE_POOL_PERSISTENT");
   p->lockstep = !(pers && pers[0] == '1');
+  const char *gr = getenv("SALE_POOL_GRAPHS");
+  p->graphs = !(gr && gr[0] == '0');
   *out = p;
   return SALE_OK;
 }
@@ -815,12 +829,38 @@ int sale_pool_advance(sale_pool *p, int32_t max_steps_per_run) {
     HIP_TRY(hipMemcpyAsync(p->d_act, p->h_act.data(), nact * sizeof(int), hipMemcpyHostToDevice, p->stream));
     HIP_TRY(hipMemcpyAsync(p->d_prefA, p->h_prefA.data(), (nact + 1) * sizeof(int), hipMemcpyHostToDevice, p->stream));
     HIP_TRY(hipMemcpyAsync(p->d_prefB, p->h_prefB.data(), (nact + 1) * sizeof(int), hipMemcpyHostToDevice, p->stream));
-    if (p->precision == SALE_FP64)
-      HIP_TRY(sale::launch_pool_lockstep<double>((const sale::PoolRun<double> *)p->d_runs, p->d_act, p->d_prefA,
-                                                 p->d_prefB, nact, totA, totB, max_steps_per_run, p->stream));
-    else
-      HIP_TRY(sale::launch_pool_lockstep<float>((const sale::PoolRun<float> *)p->d_runs, p->d_act, p->d_prefA,
-                                                p->d_prefB, nact, totA, totB, max_steps_per_run, p->stream));
+    auto rounds = [&](int n, int first, hipStream_t s) {
+      return p->precision == SALE_FP64
+                 ? sale::launch_pool_lockstep<double>((const sale::PoolRun<double> *)p->d_runs, p->d_act,
+                                                      p->d_prefA, p->d_prefB, nact, totA, totB, n, first, s)
+                 : sale::launch_pool_lockstep<float>((const sale::PoolRun<float> *)p->d_runs, p->d_act,
+                                                     p->d_prefA, p->d_prefB, nact, totA, totB, n, first, s);
+    };
+    if (!p->graphs || max_steps_per_run < 2) {
+      HIP_TRY(rounds(max_steps_per_run, 1, p->stream));
+      return SALE_OK;
+    }
+    HIP_TRY(rounds(1, 1, p->stream));
+    if (!p->round_graph || p->g_nact != nact || p->g_totA != totA || p->g_totB != totB) {
+      if (p->round_graph) {
+        HIP_TRY(hipGraphExecDestroy(p->round_graph));
+        p->round_graph = nullptr;
+      }
+      if (!p->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
+      HIP_TRY(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
+      const hipError_t le = rounds(1, 0, p->cap_stream);
+      hipGraph_t g = nullptr;
+      hipError_t e = hipStreamEndCapture(p->cap_stream, &g);
+      if (le != hipSuccess) e = le;
+      if (e == hipSuccess) e = hipGraphInstantiate(&p->round_graph, g, nullptr, nullptr, 0);
+      if (g) (void)hipGraphDestroy(g);
+      if (e != hipSuccess) {
+        p->round_graph = nullptr;
+        return hip_fail(e, "sale_pool_advance (round graph)");
+      }
+      p->g_nact = nact, p->g_totA = totA, p->g_totB = totB;
+    }
+    for (int r = 1; r < max_steps_per_run; r++) HIP_TRY(hipGraphLaunch(p->round_graph, p->stream));
     return SALE_OK;
   }
   p->h_q.head = 0;

@@ -250,10 +250,11 @@ hipError_t launch_pool_advance(PoolRun<R> *runs, const int *act, const int *pref
 // Lockstep advance: `rounds` rounds of (begin, Lagrange tiles of all runs,
 // remap tiles of all runs, clock stamp), the grids of the run descriptors
 // and the prefix sums of their block counts (prefA, prefB, nact + 1 entries)
-// describing the launches.
+// describing the launches; `first`: the first of these rounds opens the
+// advance (step targets and first clocks are set).
 template <typename R>
 hipError_t launch_pool_lockstep(const PoolRun<R> *runs, const int *act, const int *prefA, const int *prefB,
-                                int nact, int totA, int totB, int rounds, hipStream_t s);
+                                int nact, int totA, int totB, int rounds, int first, hipStream_t s);
 // Blocks of the persistent kernel that fit on the device at once.
 template <typename R>
 int pool_resident_blocks();

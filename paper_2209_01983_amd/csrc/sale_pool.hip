@@ -183,11 +183,14 @@ __global__ __launch_bounds__(NT, SALE_WAVES_POOL) void k_pool(const PoolRun<R> *
 }
 
 // ---- lockstep advance: one launch per phase over the tiles of every active run
-// A round is three launches: begin (dt and done of every run), the Lagrange
-// tiles of all runs, the remap tiles of all runs. Kernel boundaries order the
-// phases, so nothing waits on the device; a run that is done skips its tiles
-// (its state stays in its buffer). Each run's grids carry a z split sized to
-// its share of the advance's cells.
+// A round is four launches: begin (dt and done of every run), the Lagrange
+// tiles of all runs, the remap tiles of all runs, the clock stamp of the
+// runs' completed steps. Kernel boundaries order the phases, so nothing waits
+// on the device; a run that is done skips its tiles (its state stays in its
+// buffer). Each run's grids carry a z split sized to its share of the
+// advance's cells. Kernel arguments never change between the rounds of an
+// advance (the run descriptors and tables live in device memory), so every
+// round after the first can be the replay of one captured graph.
 template <typename R>
 __global__ void k_lock_begin(const PoolRun<R> *__restrict__ runs, const int *__restrict__ act, int nact,
                              int first) {
@@ -247,10 +250,10 @@ __global__ void k_lock_stamp(const PoolRun<R> *__restrict__ runs, const int *__r
 
 template <typename R>
 hipError_t launch_pool_lockstep(const PoolRun<R> *runs, const int *act, const int *prefA, const int *prefB,
-                                int nact, int totA, int totB, int rounds, hipStream_t s) {
+                                int nact, int totA, int totB, int rounds, int first, hipStream_t s) {
   const int nb = (nact + 255) / 256;
   for (int r = 0; r < rounds; r++) {
-    hipLaunchKernelGGL(k_lock_begin<R>, dim3(nb), dim3(256), 0, s, runs, act, nact, r == 0 ? 1 : 0);
+    hipLaunchKernelGGL(k_lock_begin<R>, dim3(nb), dim3(256), 0, s, runs, act, nact, first && r == 0 ? 1 : 0);
     hipLaunchKernelGGL(k_lock_lagrange<R>, dim3(totA), dim3(NT), 0, s, runs, act, prefA, nact);
     hipLaunchKernelGGL(k_lock_remap<R>, dim3(totB), dim3(NT), 0, s, runs, act, prefB, nact);
     hipLaunchKernelGGL(k_lock_stamp<R>, dim3(nb), dim3(256), 0, s, runs, act, nact);
@@ -260,9 +263,9 @@ hipError_t launch_pool_lockstep(const PoolRun<R> *runs, const int *act, const in
   return hipSuccess;
 }
 template hipError_t launch_pool_lockstep<double>(const PoolRun<double> *, const int *, const int *, const int *,
-                                                 int, int, int, int, hipStream_t);
+                                                 int, int, int, int, int, hipStream_t);
 template hipError_t launch_pool_lockstep<float>(const PoolRun<float> *, const int *, const int *, const int *, int,
-                                                int, int, int, hipStream_t);
+                                                int, int, int, int, hipStream_t);
 
 template <typename R>
 hipError_t launch_pool_advance(PoolRun<R> *runs, const int *act, const int *prefA, const int *prefB,
