@@ -31,9 +31,11 @@ FLAGS = [
 ]
 
 
-def build_lib(verbose: bool = False, extra=()) -> str:
-    """Compile every source into libsale.so (always rebuilds)."""
-    tmp = LIB + ".tmp"
+def build_lib(verbose: bool = False, extra=(), out: str = LIB) -> str:
+    """Compile every source into libsale.so (always rebuilds). `extra`: more
+    hipcc flags (e.g. -DSALE_WAVES_POOL=4 for a variant build); `out`: where
+    the library goes (a variant is loaded by naming it in SALE_LIB)."""
+    tmp = out + ".tmp"
     cmd = [HIPCC, *FLAGS, *extra, "-o", tmp] + [os.path.join(CSRC, s) for s in SOURCES]
     if verbose:
         print(" ".join(cmd), flush=True)
@@ -44,9 +46,16 @@ def build_lib(verbose: bool = False, extra=()) -> str:
         raise RuntimeError(f"hipcc failed ({r.returncode}):\n{r.stderr}")
     if verbose and errs:
         print(errs, file=sys.stderr)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":
-    print(build_lib(verbose=True))
+    import argparse
+
+    ap = argparse.ArgumentParser(description="build libsale.so for gfx950")
+    ap.add_argument("-D", dest="defines", action="append", default=[], metavar="NAME=VALUE",
+                    help="a preprocessor definition of a variant build (repeatable)")
+    ap.add_argument("--out", default=LIB, help="output path (default: next to the binding)")
+    a = ap.parse_args()
+    print(build_lib(verbose=True, extra=[f"-D{d}" for d in a.defines], out=os.path.abspath(a.out)))
