@@ -55,7 +55,10 @@ extern "C" {
 #define SALE_ENUMERIC (-4) /* non-finite / non-positive density, negative
                               or non-finite energy, non-finite dt          */
 #define SALE_ETANGLE (-5) /* a predictor or Lagrangian cell volume <= 0   */
-#define SALE_EBUSY (-6)   /* pool admission refused (no slot or budget)   */
+#define SALE_EBUSY (-6)   /* pool admission refused for now (no free slot
+                             or arena range; retry after a release) --
+                             apart from SALE_ENOMEM, which a retry cannot
+                             cure                                          */
 
 /* ---- enums ------------------------------------------------------------- */
 #define SALE_FP64 0       /* every quantity in FP64                      */
@@ -243,9 +246,9 @@ int sale_fields(sale_ctx *ctx, uint32_t mask, void *const *dst, int dst_on_devic
 int sale_step_timed(sale_ctx *ctx, int32_t n, float ms[3]);
 
 /* Launch shape of the context's two step kernels (a tuning knob; results do
- * not depend on it): tiles of 36 x rows columns (32 owned in x) for the
- * Lagrangian kernel and the remap kernel (rows 7, 14 or 28; default 14 and
- * 14, the remap 7 on meshes at most 3 cells across in y), and the
+ * not depend on it): tiles of 35 x rows columns for the Lagrangian kernel and
+ * 36 x rows for the remap kernel, 32 owned in x (rows 7, 14 or 28; default 14
+ * and 14, the remap 7 on meshes at most 3 cells across in y), and the
  * number of blocks the split of the z extent into segments aims at (0, the
  * default: automatic -- a small mesh is split as finely as the chip holds its
  * blocks at once, a large one aims at 3072 blocks). Synchronises the stream.
@@ -292,9 +295,10 @@ int sale_pool_create(int32_t precision, int32_t max_runs, void *d_arena, size_t 
 /* Admit a run: carve its workspace from the arena, enqueue its initial state
  * and return its slot. The run stops after n_steps steps or at cfg->t_end,
  * whichever comes first. cfg->precision must equal the pool's; remap order 1
- * and SALE_EULERIAN only (SALE_EINVAL otherwise). SALE_EBUSY if no slot is
- * free or no free arena range is large enough (the caller retries after a
- * release). Synchronises the stream before returning (the run's descriptor
+ * and SALE_EULERIAN only (SALE_EINVAL otherwise). SALE_ENOMEM if the run's
+ * workspace is larger than the arena's room for runs (it would never fit);
+ * SALE_EBUSY if no slot is free or no free arena range is large enough now
+ * (the caller retries after a release). Synchronises the stream before returning (the run's descriptor
  * is copied from host memory), so the admission waits for the work already
  * on the stream. */
 int sale_pool_admit(sale_pool *pool, const sale_config *cfg, const sale_problem *prob, int64_t n_steps,

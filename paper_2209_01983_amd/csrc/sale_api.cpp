@@ -730,6 +730,8 @@ int sale_pool_admit(sale_pool *p, const sale_config *cfg, const sale_problem *pr
   const Mesh m = make_mesh(cfg);
   if (m.order != 1 || m.mode != 0) return SALE_EINVAL;  // the persistent kernel: Eulerian, first order
   if ((rc = validate_problem(prob, m)) != SALE_OK) return rc;
+  const size_t bytes = a256(ws_bytes_for(m, p->precision));
+  if (bytes > p->arena_bytes - p->hdr_bytes) return SALE_ENOMEM;  // would never fit
   int s = -1;
   for (int k = 0; k < p->max_runs; k++)
     if (!p->slots[k].used) {
@@ -737,7 +739,6 @@ int sale_pool_admit(sale_pool *p, const sale_config *cfg, const sale_problem *pr
       break;
     }
   if (s < 0) return SALE_EBUSY;
-  const size_t bytes = a256(ws_bytes_for(m, p->precision));
   size_t off;
   if (!pool_alloc(p, bytes, &off)) return SALE_EBUSY;
   PoolSlot &sl = p->slots[s];
@@ -798,17 +799,18 @@ int sale_pool_advance(sale_pool *p, int32_t max_steps_per_run) {
   }
   const int nact = (int)p->h_act.size();
   if (nact == 0) return SALE_OK;
-  if (p->lockstep) {
+  {
     // z split of each run sized to its share of the advance's cells, about
-    // kLockBlocks blocks per launch in all (one segment for runs too small)
-    constexpr double kLockBlocks = 3072.0;
+    // `target` tiles per phase in all (one segment for runs too small, and
+    // for every run when the target is 0)
+    const double target = p->lockstep ? 3072.0 : (double)SALE_POOL_PERSISTENT_BLOCKS;
     double cells = 0.0;
     for (int k : p->h_act) cells += (double)p->slots[k].m.ncell;
     p->h_prefA.assign(1, 0);
     p->h_prefB.assign(1, 0);
     for (int k : p->h_act) {
       PoolSlot &sl = p->slots[k];
-      const int quota = (int)std::max(1.0, kLockBlocks * (double)sl.m.ncell / cells);
+      const int quota = (int)std::max(1.0, target * (double)sl.m.ncell / cells);
       const sale::Grid2 ga = sale::grid_lagrange(sl.m, quota, sale::kPoolRows, sale::kPoolWidth);
       const sale::Grid2 gb = sale::grid_remap(sl.m, quota, sale::kPoolRows, sale::kPoolWidth);
       hipError_t ce;
@@ -825,10 +827,12 @@ int sale_pool_advance(sale_pool *p, int32_t max_steps_per_run) {
       p->h_prefA.push_back(p->h_prefA.back() + ga.blocks());
       p->h_prefB.push_back(p->h_prefB.back() + gb.blocks());
     }
-    const int totA = p->h_prefA.back(), totB = p->h_prefB.back();
-    HIP_TRY(hipMemcpyAsync(p->d_act, p->h_act.data(), nact * sizeof(int), hipMemcpyHostToDevice, p->stream));
-    HIP_TRY(hipMemcpyAsync(p->d_prefA, p->h_prefA.data(), (nact + 1) * sizeof(int), hipMemcpyHostToDevice, p->stream));
-    HIP_TRY(hipMemcpyAsync(p->d_prefB, p->h_prefB.data(), (nact + 1) * sizeof(int), hipMemcpyHostToDevice, p->stream));
+  }
+  const int totA = p->h_prefA.back(), totB = p->h_prefB.back();
+  HIP_TRY(hipMemcpyAsync(p->d_act, p->h_act.data(), nact * sizeof(int), hipMemcpyHostToDevice, p->stream));
+  HIP_TRY(hipMemcpyAsync(p->d_prefA, p->h_prefA.data(), (nact + 1) * sizeof(int), hipMemcpyHostToDevice, p->stream));
+  HIP_TRY(hipMemcpyAsync(p->d_prefB, p->h_prefB.data(), (nact + 1) * sizeof(int), hipMemcpyHostToDevice, p->stream));
+  if (p->lockstep) {
     auto rounds = [&](int n, int first, hipStream_t s) {
       return p->precision == SALE_FP64
                  ? sale::launch_pool_lockstep<double>((const sale::PoolRun<double> *)p->d_runs, p->d_act,
@@ -866,16 +870,12 @@ int sale_pool_advance(sale_pool *p, int32_t max_steps_per_run) {
   p->h_q.head = 0;
   p->h_q.nact = nact;
   p->h_q.rounds = max_steps_per_run;
-  p->h_q.totA = p->h_prefA.back();
-  p->h_q.totB = p->h_prefB.back();
+  p->h_q.totA = totA;
+  p->h_q.totB = totB;
   p->h_q.timeouts = 0;
   p->h_q.abort = 0;
-  const unsigned long long items =
-      (unsigned long long)(p->h_q.totA + p->h_q.totB) * (unsigned long long)max_steps_per_run;
+  const unsigned long long items = (unsigned long long)(totA + totB) * (unsigned long long)max_steps_per_run;
   const int blocks = (int)std::min<unsigned long long>((unsigned long long)p->resident, items);
-  HIP_TRY(hipMemcpyAsync(p->d_act, p->h_act.data(), nact * sizeof(int), hipMemcpyHostToDevice, p->stream));
-  HIP_TRY(hipMemcpyAsync(p->d_prefA, p->h_prefA.data(), (nact + 1) * sizeof(int), hipMemcpyHostToDevice, p->stream));
-  HIP_TRY(hipMemcpyAsync(p->d_prefB, p->h_prefB.data(), (nact + 1) * sizeof(int), hipMemcpyHostToDevice, p->stream));
   HIP_TRY(hipMemcpyAsync(p->d_q, &p->h_q, sizeof(p->h_q), hipMemcpyHostToDevice, p->stream));
   if (p->precision == SALE_FP64)
     HIP_TRY(sale::launch_pool_advance<double>((sale::PoolRun<double> *)p->d_runs, p->d_act, p->d_prefA, p->d_prefB,

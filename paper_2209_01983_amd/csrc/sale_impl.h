@@ -241,6 +241,12 @@ struct PoolQueue {
 #define SALE_POOL_ROWS 16
 #endif
 constexpr int kPoolRows = SALE_POOL_ROWS, kPoolWidth = 32;
+// Tiles per phase the persistent advance splits the runs' z extents into, in
+// proportion to their cells (0: one z segment per tile column). The lockstep
+// advance aims at 3072 blocks per launch.
+#ifndef SALE_POOL_PERSISTENT_BLOCKS
+#define SALE_POOL_PERSISTENT_BLOCKS 0
+#endif
 
 // Persistent multi-run advance: prepare (queue head, per-run counters, first
 // dt) and the persistent kernel over `blocks` blocks; tables on the device.

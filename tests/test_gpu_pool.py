@@ -7,7 +7,8 @@ count to 1e-12 per field (the single-run bar); a run's results are bitwise
 the same alone in a pool, among other runs of uneven sizes, and on the
 single-run path (the arithmetic per cell does not depend on tiling or on
 pool-mates); slots and arena ranges are reused after release; admission
-refuses with SALE_EBUSY when no slot or no arena range is free; an error flag
+refuses with SALE_EBUSY when no slot or no arena range is free (SALE_ENOMEM
+for a run that could never fit); an error flag
 of one run stops that run only.
 """
 import numpy as np
@@ -156,6 +157,11 @@ def test_pool_slots_and_arena_are_reused_and_admission_refuses_when_full():
     d = pool.admit(small, sale.sedov_problem(), 3)
     e = pool.admit(small, sale.sedov_problem(), 3)
     assert d is not None and e is None                                 # 4 slots
+    # a run larger than the arena's room for runs can never be admitted: ENOMEM, not EBUSY
+    big = sale.make_config(64, 64, 64, hi=(1.2, 1.2, 1.2), t_end=1.0)
+    with pytest.raises(sale.SaleError) as err:
+        pool.admit(big, sale.sedov_problem(), 3)
+    assert err.value.code == sale.SALE_ENOMEM
     done = drain(pool, 3, 4)
     assert sorted(done) == sorted([a, b, c, d])
     ref = pool.fields(a)
