@@ -35,6 +35,7 @@ def build_lib(verbose: bool = False, extra=(), out: str = LIB) -> str:
     """Compile every source into libsale.so (always rebuilds). `extra`: more
     hipcc flags (e.g. -DSALE_WAVES_POOL=4 for a variant build); `out`: where
     the library goes (a variant is loaded by naming it in SALE_LIB)."""
+    os.makedirs(os.path.dirname(os.path.abspath(out)), exist_ok=True)
     tmp = out + ".tmp"
     cmd = [HIPCC, *FLAGS, *extra, "-o", tmp] + [os.path.join(CSRC, s) for s in SOURCES]
     if verbose:

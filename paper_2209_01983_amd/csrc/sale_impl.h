@@ -121,7 +121,8 @@ template <typename R>
 hipError_t launch_positions(const Mesh &m, const Work<R> &w, int cur, int axis, double *out, hipStream_t s);
 
 // The second-order remap (multi-pass kernels in sale_remap2.hip): from the
-// Lagrangian results in w.geo / u' into w.s[1 - cur], then the next signal
+// Lagrangian results in w.geo (rho^L included: the second-order step's
+// Lagrange kernel forms it) / u' into w.s[1 - cur], then the next signal
 // speed into ctl.
 template <typename R>
 hipError_t launch_remap2(const Mesh &m, Ctl *ctl, const Work<R> &w, int cur, hipStream_t s);

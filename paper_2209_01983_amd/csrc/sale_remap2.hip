@@ -13,9 +13,9 @@
 // masses, the dual fluxes, the kinetic-energy fix, walls, the next signal
 // speed -- is the first-order step's.
 //
-// The Lagrangian densities first (one thread per cell), then three passes,
-// each a 32 x 16 tile of columns marched along z (every input value read
-// from memory once per tile, neighbours through LDS):
+// The step's Lagrange kernel hands over rho^L as well (its tile's fifth
+// phase); then three passes, each a tile of columns marched along z (every
+// input value read from memory once per tile, neighbours through LDS):
 //   k_cells2  fluxes through each cell's six faces, M, rho^{n+1}, e^pre
 //   k_nodes2  dual fluxes, reconstructed donor velocities, u^{n+1}, KE defect
 //   k_fix2    KE fix, e^{n+1}, the next signal speed (block max -> ctl)
@@ -24,7 +24,6 @@
 
 namespace sale {
 namespace {
-
 
 // Harmonic mean of two one-sided differences of neighbouring means (zero
 // where they differ in sign): the limited change of the profile over one
@@ -52,57 +51,32 @@ __device__ __forceinline__ R donor_value(R q, R dq, R wgt, bool lower) {
 }
 
 
-// ---- pass 0: Lagrangian densities -------------------------------------------------------
-// rho^L = m / V^L of every cell, V^L = V0 + the swept volumes of its six faces
-// (the Lagrange tile hands over each cell's three lower faces; an upper face
-// is the lower face of the +axis neighbour, zero on a wall). A cell with
-// V^L <= 0 is tangled: flag, and rho^L = 0.
-template <typename R>
-__global__ __launch_bounds__(256) void k_rho_lag(Mesh m, Ctl *ctl, State<R> cur, Geo<R> geo) {
-  if (ctl->done) return;
-  const int64_t c = blockIdx.x * (int64_t)256 + threadIdx.x;
-  if (c >= m.ncell) return;
-  const int i = (int)(c % m.nx);
-  const int64_t r = c / m.nx;
-  const int j = (int)(r % m.ny), k = (int)(r / m.ny);
-  const int64_t cpl = (int64_t)m.nx * m.ny;
-  const double vxu = i + 1 < m.nx ? (double)geo.dvx[c + 1] : 0.0;
-  const double vyu = j + 1 < m.ny ? (double)geo.dvy[c + m.nx] : 0.0;
-  const double vzu = k + 1 < m.nz ? (double)geo.dvz[c + cpl] : 0.0;
-  const double VL =
-      m.V0 + (((vxu - (double)geo.dvx[c]) + (vyu - (double)geo.dvy[c])) + (vzu - (double)geo.dvz[c]));
-  const R mc = cur.rho[c] * R(m.V0);
-  double rl = 0.0;
-  if (!(VL > 0.0))
-    atomicOr(&ctl->status, SALE_FLAG_TANGLE);
-  else
-    rl = (double)mc / VL;
-  geo.rl[c] = R(rl);
-}
-
 // ---- pass 1: face fluxes, cell masses, densities, pre-fix energies --------------------
-// A 32 x 16 tile of cell columns (halo 2 on each side: a face's donor
-// profile reaches one cell beyond the donor) marched along z over one
-// segment. Each cell forms the fluxes of its lower and upper faces on all
+// A 36 x 14 tile of cell columns owning 32 x 10 (halo 2 on each side: a
+// face's donor profile reaches one cell beyond the donor; the owned columns
+// start on a multiple of 32, so every stored row is whole 128-byte lines)
+// marched along z over one segment; 512 threads, the 8 spare ones own
+// nothing. Each cell forms the fluxes of its lower and upper faces on all
 // three axes; a face shared by two cells is formed by both from the same
 // operands, so both get the same bits. The LDS holds rho^L, e^L and the x/y
 // swept volumes of the cell plane; rho^L and e^L of cell planes k-2..k+2 (the
 // z profiles) are carried in registers. Stores the lower faces' mass fluxes
 // (for the node pass), M, rho^{n+1} and e^pre.
-constexpr int CW2 = 32, CH2 = 16, CTX = CW2 - 4, CTY = CH2 - 4;
+constexpr int CW2 = 36, CH2 = 14, CTX = CW2 - 4, CTY = CH2 - 4;
+constexpr int NT2 = (CW2 * CH2 + 63) / 64 * 64, CH2L = (NT2 + CW2 - 1) / CW2;  // threads; LDS rows
 
 template <typename R>
-__global__ __launch_bounds__(CW2 * CH2) void k_cells2(Mesh m, Ctl *ctl, State<R> cur, State<R> nxt, Geo<R> geo,
-                                                     Rem2<R> t, Grid2 g) {
+__global__ __launch_bounds__(NT2) void k_cells2(Mesh m, Ctl *ctl, State<R> cur, State<R> nxt, Geo<R> geo,
+                                              Rem2<R> t, Grid2 g) {
   enum { RL, EL, DX, DY, NPL };
-  __shared__ R L[NPL][CH2][CW2];
+  __shared__ R L[NPL][CH2L][CW2];  // (row CH2: the spare threads' own, never read)
   int tx, ty, seg;
   tile_of(g, blockIdx.x, tx, ty, seg);
-  const int ci = threadIdx.x % CW2, cj = threadIdx.x / CW2;
+  const int ci = threadIdx.x % CW2, cj = threadIdx.x / CW2;  // cj == CH2: a spare thread
   const int gi = tx * CTX + ci - 2, gj = ty * CTY + cj - 2;  // cell column
   const int Z0 = seg * g.seglen;
   const int Z1 = seg == g.nseg - 1 ? m.nz : Z0 + g.seglen;  // cell planes [Z0, Z1)
-  const bool ccol = gi >= 0 && gi < m.nx && gj >= 0 && gj < m.ny;
+  const bool ccol = cj < CH2 && gi >= 0 && gi < m.nx && gj >= 0 && gj < m.ny;
   const bool own = ci >= 2 && cj >= 2 && ci < 2 + CTX && cj < 2 + CTY && ccol;
   const int64_t cpl = (int64_t)m.nx * m.ny;
   const int64_t cix = ccol ? gi + (int64_t)m.nx * gj : 0;
@@ -589,8 +563,7 @@ hipError_t launch_remap2(const Mesh &m, Ctl *ctl, const Work<R> &w, int cur, hip
   const Grid2 gnode = tiles(m.nx + 1, m.ny + 1, m.nz + 1, NTX, NTY);
   const Grid2 gf = tiles(m.nx, m.ny, m.nz, FTX, FTY);
   const Grid2 gcell = tiles(m.nx, m.ny, m.nz, CTX, CTY);
-  hipLaunchKernelGGL(k_rho_lag<R>, dim3((unsigned)((m.ncell + 255) / 256)), dim3(256), 0, s, m, ctl, sc, w.geo);
-  hipLaunchKernelGGL(k_cells2<R>, dim3((unsigned)gcell.blocks()), dim3(CW2 * CH2), 0, s, m, ctl, sc, sn, w.geo, w.r2,
+  hipLaunchKernelGGL(k_cells2<R>, dim3((unsigned)gcell.blocks()), dim3(NT2), 0, s, m, ctl, sc, sn, w.geo, w.r2,
                      gcell);
   hipLaunchKernelGGL(k_nodes2<R>, dim3((unsigned)gnode.blocks()), dim3(NW * NH), 0, s, m, ctl, sc, sn, w.geo, w.up,
                      w.vp, w.wp, w.r2, gnode);

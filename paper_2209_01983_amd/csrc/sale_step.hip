@@ -37,11 +37,13 @@ __global__ void k_begin(Mesh m, Ctl *ctl) {
   if (threadIdx.x == 0 && blockIdx.x == 0) begin_step(m, ctl, 0x7fffffffffffffffll);
 }
 
-template <typename R, int CH>
+// (RL: the second-order step's Lagrange kernel, which also forms rho^L)
+template <typename R, int CH, bool RL = false>
 __global__ __launch_bounds__(tile_threads<CH>(), waves_of<CH>()) void k_lagrange(RunArgs<R> a) {
-  __shared__ double lds[lagrange_lds_doubles<CH>()];
+  __shared__ double lds[lagrange_lds_doubles<CH, kTileWL, tile_threads<CH>(), RL>()];
   if (a.ctl->done) return;
-  const bool t = lagrange_tile<R, CH>(a, xcd_logical_block(blockIdx.x, gridDim.x), a.ctl->dt, lds);
+  const bool t =
+      lagrange_tile<R, CH, kTileWL, tile_threads<CH>(), RL>(a, xcd_logical_block(blockIdx.x, gridDim.x), a.ctl->dt, lds);
   if (t) atomicOr(&a.ctl->status, SALE_FLAG_TANGLE);
 }
 
@@ -557,7 +559,10 @@ RunArgs<R> run_args(const Mesh &m, Ctl *ctl, const Work<R> &w, int cur, const La
 
 template <typename R, int CH>
 void launch_lagrange(const RunArgs<R> &a, hipStream_t s) {
-  hipLaunchKernelGGL((k_lagrange<R, CH>), dim3(a.ga.blocks()), dim3(tile_threads<CH>()), 0, s, a);
+  if (a.m.order == 2)  // the second-order remap's passes take rho^L from the Lagrange kernel
+    hipLaunchKernelGGL((k_lagrange<R, CH, true>), dim3(a.ga.blocks()), dim3(tile_threads<CH>()), 0, s, a);
+  else
+    hipLaunchKernelGGL((k_lagrange<R, CH>), dim3(a.ga.blocks()), dim3(tile_threads<CH>()), 0, s, a);
 }
 template <typename R, int CH>
 void launch_remap(const RunArgs<R> &a, hipStream_t s) {

@@ -151,10 +151,10 @@ constexpr int lds_rows() {
 }
 
 // LDS doubles needed by each tile function (planes of CW x lds_rows) in a
-// block of NT threads
-template <int CH, int CW = kTileWL, int NT = tile_threads<CH>()>
+// block of NT threads (RL: the Lagrange tile that also forms rho^L)
+template <int CH, int CW = kTileWL, int NT = tile_threads<CH>(), bool RL = false>
 constexpr int lagrange_lds_doubles() {
-  return 11 * CW * lds_rows<CW, CH, NT>();
+  return (RL ? 13 : 11) * CW * lds_rows<CW, CH, NT>();
 }
 // (remap: two double planes, then 16 planes of the bulk type R)
 template <typename R, int CH, int CW = kTileW, int NT = tile_threads<CH>()>
@@ -179,9 +179,13 @@ constexpr int remap_lds_doubles() {
 //       delta on node planes k-1 and k only), its compatible-energy work and
 //       e^L; hand-off to remap_tile, which forms V^L and rho^L from the six
 //       faces' swept volumes
-// Returns true if a tangled cell was seen (the predictor's volume). CW: tile
-// width, NTH: block size.
-template <typename R, int CH, int CW = kTileWL, int NTH = tile_threads<CH>()>
+//   P5  (RL only) V^L = V0 + the six faces' swept volumes and rho^L of cell
+//       plane k-1, the upper x/y faces being the +x/+y neighbours' lower
+//       faces (the first halo column and row above form theirs too), for the
+//       second-order remap's passes
+// Returns true if a tangled cell was seen (the predictor's volume; with RL
+// also V^L). CW: tile width, NTH: block size.
+template <typename R, int CH, int CW = kTileWL, int NTH = tile_threads<CH>(), bool RL = false>
 __device__ bool lagrange_tile(const RunArgs<R> &a, int b, double dtd, double *lds) {
   constexpr int TX = CW - 3, TY = CH - 3, CHL = lds_rows<CW, CH, NTH>();
   static_assert(CW * CH <= NTH, "one thread per column");
@@ -209,7 +213,9 @@ __device__ bool lagrange_tile(const RunArgs<R> &a, int b, double dtd, double *ld
   R(*sP)[CW] = reinterpret_cast<R(*)[CW]>(lds + 3 * CHL * CW);            // P*
   R(*sM)[CW] = reinterpret_cast<R(*)[CW]>(lds + 4 * CHL * CW);            // m
   double(*sD)[3][CHL][CW] = reinterpret_cast<double(*)[3][CHL][CW]>(lds + 5 * CHL * CW);  // [2][3]
-  static_assert(11 * CHL * CW <= lagrange_lds_doubles<CH, CW, NTH>(), "lagrange LDS layout");
+  double(*sVX)[CW] = reinterpret_cast<double(*)[CW]>(lds + 11 * CHL * CW);  // (RL) lower x faces
+  double(*sVY)[CW] = reinterpret_cast<double(*)[CW]>(lds + 12 * CHL * CW);  // (RL) lower y faces
+  static_assert((RL ? 13 : 11) * CHL * CW <= lagrange_lds_doubles<CH, CW, NTH, RL>(), "lagrange LDS layout");
 
   for (int q = threadIdx.x; q < 2 * 3 * CHL * CW; q += NTH) (&sD[0][0][0][0])[q] = 0.0;
 
@@ -334,8 +340,15 @@ __device__ bool lagrange_tile(const RunArgs<R> &a, int b, double dtd, double *ld
       pzd = qzd;
       const bool mine = own_cell && cp >= Z0 && cp < Z1;
       double vx = 0.0, vy = 0.0, dvz_up = 0.0;
+      // the cells whose lower x / y faces are formed: the owned ones, with RL
+      // also the first halo column (x) and row (y) above them, whose lower
+      // faces are the owned cells' upper faces (a wall face stays zero)
+      const bool fx = RL ? plane_ok && ci >= 1 && ci <= TX + 1 && cj >= 1 && cj <= TY && gi <= m.nx - 1 && gj < m.ny
+                         : mine && plane_ok;
+      const bool fy = RL ? plane_ok && ci >= 1 && ci <= TX && cj >= 1 && cj <= TY + 1 && gi < m.nx && gj <= m.ny - 1
+                         : mine && plane_ok;
       // lower x face (node column gi, between cells gi-1 and gi); corners (s: y, t: z)
-      if (mine && plane_ok && gi >= 1) {
+      if (fx && gi >= 1) {
         const double d0[3] = {A[0][cj][ci], A[1][cj][ci], A[2][cj][ci]};
         const double d1[3] = {A[0][cj + 1][ci], A[1][cj + 1][ci], A[2][cj + 1][ci]};
         const double d2[3] = {B[0][cj][ci], B[1][cj][ci], B[2][cj][ci]};
@@ -343,7 +356,7 @@ __device__ bool lagrange_tile(const RunArgs<R> &a, int b, double dtd, double *ld
         vx = swept_volume(d0, d1, d2, d3, m.ax, m.edy, m.edz);
       }
       // lower y face (node row gj, between cells gj-1 and gj); corners (s: z, t: x); comps (y, z, x)
-      if (mine && plane_ok && gj >= 1) {
+      if (fy && gj >= 1) {
         const double d0[3] = {A[1][cj][ci], A[2][cj][ci], A[0][cj][ci]};
         const double d1[3] = {B[1][cj][ci], B[2][cj][ci], B[0][cj][ci]};
         const double d2[3] = {A[1][cj][ci + 1], A[2][cj][ci + 1], A[0][cj][ci + 1]};
@@ -359,6 +372,11 @@ __device__ bool lagrange_tile(const RunArgs<R> &a, int b, double dtd, double *ld
         const double d3[3] = {B[2][cj + 1][ci + 1], B[0][cj + 1][ci + 1], B[1][cj + 1][ci + 1]};
         dvz_up = swept_volume(d0, d1, d2, d3, m.az, m.edx, m.edy);
       }
+      if constexpr (RL) {
+        // the hand-off's rounding, as the remap reads it back
+        sVX[cj][ci] = (double)R(vx);
+        sVY[cj][ci] = (double)R(vy);
+      }
       settle(fu), settle(fv), settle(fw), settle(frho), settle(fe);  // loads issued in P1
       if (mine) {
         const uint32_t oR = cix * (uint32_t)sizeof(R);
@@ -366,6 +384,20 @@ __device__ bool lagrange_tile(const RunArgs<R> &a, int b, double dtd, double *ld
         plane_at<R>(a.geo.dvx, cpl, cp, oR) = R(vx);
         plane_at<R>(a.geo.dvy, cpl, cp, oR) = R(vy);
         plane_at<R>(a.geo.dvz, cpl, cp, oR) = R(dvz_lo);
+      }
+      if constexpr (RL) {
+        // ---- P5: V^L and rho^L of cell plane k-1 ----
+        __syncthreads();
+        if (mine) {
+          const double VL = m.V0 + (((sVX[cj][ci + 1] - sVX[cj][ci]) + (sVY[cj + 1][ci] - sVY[cj][ci])) +
+                                    ((double)R(dvz_up) - (double)R(dvz_lo)));
+          R rl = R(0);
+          if (!(VL > 0.0))
+            tangle = true;
+          else
+            rl = R((double)m1 / VL);
+          plane_at<R>(a.geo.rl, cpl, cp, cix * (uint32_t)sizeof(R)) = rl;
+        }
       }
       dvz_lo = dvz_up;
     }
