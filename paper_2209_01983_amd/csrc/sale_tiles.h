@@ -179,10 +179,10 @@ constexpr int remap_lds_doubles() {
 //       delta on node planes k-1 and k only), its compatible-energy work and
 //       e^L; hand-off to remap_tile, which forms V^L and rho^L from the six
 //       faces' swept volumes
-//   P5  (RL only) V^L = V0 + the six faces' swept volumes and rho^L of cell
-//       plane k-1, the upper x/y faces being the +x/+y neighbours' lower
-//       faces (the first halo column and row above form theirs too), for the
-//       second-order remap's passes
+//   P5  (RL only) V^L = V0 + the six faces' swept volumes (FP64) and rho^L
+//       of cell plane k-1, the upper x/y faces being the +x/+y neighbours'
+//       lower faces (the first halo column and row above form theirs too),
+//       for the second-order remap's passes
 // Returns true if a tangled cell was seen (the predictor's volume; with RL
 // also V^L). CW: tile width, NTH: block size.
 template <typename R, int CH, int CW = kTileWL, int NTH = tile_threads<CH>(), bool RL = false>
@@ -372,10 +372,9 @@ __device__ bool lagrange_tile(const RunArgs<R> &a, int b, double dtd, double *ld
         const double d3[3] = {B[2][cj + 1][ci + 1], B[0][cj + 1][ci + 1], B[1][cj + 1][ci + 1]};
         dvz_up = swept_volume(d0, d1, d2, d3, m.az, m.edx, m.edy);
       }
-      if constexpr (RL) {
-        // the hand-off's rounding, as the remap reads it back
-        sVX[cj][ci] = (double)R(vx);
-        sVY[cj][ci] = (double)R(vy);
+      if constexpr (RL) {  // FP64, whatever the bulk type of the hand-off
+        sVX[cj][ci] = vx;
+        sVY[cj][ci] = vy;
       }
       settle(fu), settle(fv), settle(fw), settle(frho), settle(fe);  // loads issued in P1
       if (mine) {
@@ -389,8 +388,8 @@ __device__ bool lagrange_tile(const RunArgs<R> &a, int b, double dtd, double *ld
         // ---- P5: V^L and rho^L of cell plane k-1 ----
         __syncthreads();
         if (mine) {
-          const double VL = m.V0 + (((sVX[cj][ci + 1] - sVX[cj][ci]) + (sVY[cj + 1][ci] - sVY[cj][ci])) +
-                                    ((double)R(dvz_up) - (double)R(dvz_lo)));
+          const double VL =
+              m.V0 + (((sVX[cj][ci + 1] - sVX[cj][ci]) + (sVY[cj + 1][ci] - sVY[cj][ci])) + (dvz_up - dvz_lo));
           R rl = R(0);
           if (!(VL > 0.0))
             tangle = true;
