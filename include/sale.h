@@ -324,7 +324,9 @@ int sale_pool_fields(sale_pool *pool, int32_t slot, uint32_t mask, void *const *
 /* Return a slot and its arena range to the pool (synchronises the stream). */
 int sale_pool_release(sale_pool *pool, int32_t slot);
 
-/* Free the pool's host memory (the arena stays the caller's). */
+/* Free the pool's host memory, its capture stream and its round graph (the
+ * arena stays the caller's). If a round graph exists, the stream is
+ * synchronised first, so that no queued replay outlives it. */
 void sale_pool_destroy(sale_pool *pool);
 
 /* Static description of a return code (SALE_EHIP: the last HIP error of the

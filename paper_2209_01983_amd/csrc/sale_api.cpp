@@ -611,7 +611,10 @@ struct sale_pool {
   hipGraphExec_t round_graph = nullptr;
   int g_nact = -1, g_totA = -1, g_totB = -1;
   ~sale_pool() {
-    if (round_graph) (void)hipGraphExecDestroy(round_graph);
+    if (round_graph) {
+      (void)hipStreamSynchronize(stream);  // replays of it may still be queued
+      (void)hipGraphExecDestroy(round_graph);
+    }
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
   }
 };
