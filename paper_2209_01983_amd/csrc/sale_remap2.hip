@@ -216,23 +216,28 @@ __global__ __launch_bounds__(NT2) void k_cells2(Mesh m, Ctl *ctl, State<R> cur, 
 // are carried in registers, formed in the previous pass). u' of node planes
 // k-2..k+2 (the z profiles) is carried in registers. Each input value is
 // read from memory once per tile.
-constexpr int NW = 32, NH = 16, NTX = NW - 4, NTY = NH - 4;
+// (36 x 14 tiles owning 32 x 10 nodes ran slower here: 1.32 -> 1.44 ms at
+// 320^3; the node arrays' rows do not start on 128-byte lines anyway)
+constexpr int NW = 32, NH = 16;
+constexpr int NTX = NW - 4, NTY = NH - 4;
+constexpr int NT3 = (NW * NH + 63) / 64 * 64, NHL = (NT3 + NW - 1) / NW;  // threads; LDS rows
 
 template <typename R>
-__global__ __launch_bounds__(NW * NH, 4) void k_nodes2(Mesh m, Ctl *ctl, State<R> cur, State<R> nxt, Geo<R> geo,
-                                                   const R *up, const R *vp, const R *wp, Rem2<R> t, Grid2 g) {
+__global__ __launch_bounds__(NT3, 4) void k_nodes2(Mesh m, Ctl *ctl, State<R> cur, State<R> nxt, Geo<R> geo,
+                                               const R *up, const R *vp, const R *wp, Rem2<R> t, Grid2 g) {
   enum { MX, MY, VX, VY, SZ, VZ, MO, MN, NCP };
-  __shared__ R LU[3][NH][NW];    // u', v', w' of node plane k
-  __shared__ R LC[NCP][NH][NW];  // MX..VY, MO, MN: cell planes k-1 + k; SZ, VZ: plane k
-  __shared__ R LP[6][NH][NW];    // the thread's own column at cell plane k-1 (private)
+  __shared__ R LU[3][NHL][NW];    // u', v', w' of node plane k
+  __shared__ R LC[NCP][NHL][NW];  // MX..VY, MO, MN: cell planes k-1 + k; SZ, VZ: plane k
+  __shared__ R LP[6][NHL][NW];    // the thread's own column at cell plane k-1 (private)
+  // (row NH of each: the spare threads' own, never read by a stencil)
   int tx, ty, seg;
   tile_of(g, blockIdx.x, tx, ty, seg);
-  const int ci = threadIdx.x % NW, cj = threadIdx.x / NW;
+  const int ci = threadIdx.x % NW, cj = threadIdx.x / NW;  // cj == NH: a spare thread
   const int gi = tx * NTX + ci - 2, gj = ty * NTY + cj - 2;  // node column, and cell column (gi, gj)
   const int Z0 = seg * g.seglen;
   const int NZ1 = seg == g.nseg - 1 ? m.nz + 1 : Z0 + g.seglen;  // node planes [Z0, NZ1)
-  const bool ncol = gi >= 0 && gi <= m.nx && gj >= 0 && gj <= m.ny;
-  const bool ccol = gi >= 0 && gi < m.nx && gj >= 0 && gj < m.ny;
+  const bool ncol = cj < NH && gi >= 0 && gi <= m.nx && gj >= 0 && gj <= m.ny;
+  const bool ccol = cj < NH && gi >= 0 && gi < m.nx && gj >= 0 && gj < m.ny;
   const bool own = ci >= 2 && cj >= 2 && ci < 2 + NTX && cj < 2 + NTY && gi <= m.nx && gj <= m.ny;
   const int64_t cpl = (int64_t)m.nx * m.ny, npl = (int64_t)(m.nx + 1) * (m.ny + 1);
   const int64_t cix = ccol ? gi + (int64_t)m.nx * gj : 0, nix = ncol ? gi + (int64_t)(m.nx + 1) * gj : 0;
@@ -301,7 +306,7 @@ __global__ __launch_bounds__(NW * NH, 4) void k_nodes2(Mesh m, Ctl *ctl, State<R
   // from the previous pass
   R zs_m = R(0), zs_v = R(0);
   for (int k = K0; k < NZ1; k++) {
-    R(*const C)[NH][NW] = LC;
+    R(*const C)[NHL][NW] = LC;
     LU[0][cj][ci] = zu[2];
     LU[1][cj][ci] = zv[2];
     LU[2][cj][ci] = zw[2];
@@ -328,24 +333,24 @@ __global__ __launch_bounds__(NW * NH, 4) void k_nodes2(Mesh m, Ctl *ctl, State<R
     node_load(k + 3, nu, nv, nw);
     __syncthreads();
     // sums over the 4 cell columns around the node (zero where absent)
-    auto c4 = [&](R(*P)[NH][NW], int s) {
+    auto c4 = [&](R(*P)[NHL][NW], int s) {
       return ((P[s][cj - 1][ci - 1] + P[s][cj - 1][ci]) + P[s][cj][ci - 1]) + P[s][cj][ci];
     };
     // the z dual faces above node plane k: those of the 4 cells of plane k
     const R za_m = own ? R(0.125) * c4(C, SZ) : R(0), za_v = own ? R(0.125) * c4(C, VZ) : R(0);
     if (own && k >= Z0) {
       // x edges: cells (i, j-1..j) (outflow) and (i-1, j-1..j) (inflow), lower + upper face each
-      auto xo = [&](R(*P)[NH][NW], int s) {
+      auto xo = [&](R(*P)[NHL][NW], int s) {
         return (P[s][cj - 1][ci] + P[s][cj - 1][ci + 1]) + (P[s][cj][ci] + P[s][cj][ci + 1]);
       };
-      auto xi = [&](R(*P)[NH][NW], int s) {
+      auto xi = [&](R(*P)[NHL][NW], int s) {
         return (P[s][cj - 1][ci - 1] + P[s][cj - 1][ci]) + (P[s][cj][ci - 1] + P[s][cj][ci]);
       };
       // y edges: cells (i-1..i, j) (outflow) and (i-1..i, j-1) (inflow)
-      auto yo = [&](R(*P)[NH][NW], int s) {
+      auto yo = [&](R(*P)[NHL][NW], int s) {
         return (P[s][cj][ci - 1] + P[s][cj + 1][ci - 1]) + (P[s][cj][ci] + P[s][cj + 1][ci]);
       };
-      auto yi = [&](R(*P)[NH][NW], int s) {
+      auto yi = [&](R(*P)[NHL][NW], int s) {
         return (P[s][cj - 1][ci - 1] + P[s][cj][ci - 1]) + (P[s][cj - 1][ci] + P[s][cj][ci]);
       };
       {
@@ -459,24 +464,28 @@ __global__ __launch_bounds__(NW * NH, 4) void k_nodes2(Mesh m, Ctl *ctl, State<R
 }
 
 // ---- pass 3: kinetic-energy fix, new energy, next signal speed ------------------------
-// A 32 x 16 tile of node columns marched along z over one segment: each
-// node plane's u^{n+1}, v, w and KE defect are read once into LDS, a cell
-// column forms its lower-plane half (partial defect sum, largest |u|^2,
-// divergence halves) and finishes the cell when the upper plane arrives.
-// Sums run in the order of the cell's 8 nodes (x fastest, then y, then z),
-// as in the gather form of the same pass.
-constexpr int FW = 32, FH = 16, FTX = FW - 1, FTY = FH - 1;
+// A 33 x 15 tile of node columns (512 threads, 17 spare) owning 32 x 14
+// cells, marched along z over one segment: each node plane's u^{n+1}, v, w
+// and KE defect are read once into LDS, a cell column forms its lower-plane
+// half (partial defect sum, largest |u|^2, divergence halves) and finishes
+// the cell when the upper plane arrives. Sums run in the order of the
+// cell's 8 nodes (x fastest, then y, then z), as in the gather form of the
+// same pass. The owned cells of a row start on a multiple of 32, so the
+// stored energies fill whole 128-byte lines.
+constexpr int FW = 33, FH = 15;
+constexpr int FTX = FW - 1, FTY = FH - 1;
+constexpr int NT4 = (FW * FH + 63) / 64 * 64, FHL = (NT4 + FW - 1) / FW;  // threads; LDS rows
 
 template <typename R>
-__global__ __launch_bounds__(FW * FH) void k_fix2(Mesh m, Ctl *ctl, State<R> cur, State<R> nxt, Rem2<R> t, Grid2 g) {
-  __shared__ R sU[FH][FW], sV[FH][FW], sW[FH][FW], sQ[FH][FW];
+__global__ __launch_bounds__(NT4) void k_fix2(Mesh m, Ctl *ctl, State<R> cur, State<R> nxt, Rem2<R> t, Grid2 g) {
+  __shared__ R sU[FHL][FW], sV[FHL][FW], sW[FHL][FW], sQ[FHL][FW];  // (row FH: the spare threads')
   int tx, ty, seg;
   tile_of(g, blockIdx.x, tx, ty, seg);
-  const int ci = threadIdx.x % FW, cj = threadIdx.x / FW;
+  const int ci = threadIdx.x % FW, cj = threadIdx.x / FW;  // cj == FH: a spare thread
   const int gi = tx * FTX + ci, gj = ty * FTY + cj;  // node column; cell column when owned
   const int Z0 = seg * g.seglen;
   const int Z1 = seg == g.nseg - 1 ? m.nz : Z0 + g.seglen;  // cell planes [Z0, Z1)
-  const bool ncol = gi <= m.nx && gj <= m.ny;
+  const bool ncol = cj < FH && gi <= m.nx && gj <= m.ny;
   const bool own = ci < FTX && cj < FTY && gi < m.nx && gj < m.ny;
   const int64_t cpl = (int64_t)m.nx * m.ny, npl = (int64_t)(m.nx + 1) * (m.ny + 1);
   const int64_t cix = own ? gi + (int64_t)m.nx * gj : 0, nix = ncol ? gi + (int64_t)(m.nx + 1) * gj : 0;
@@ -538,7 +547,7 @@ __global__ __launch_bounds__(FW * FH) void k_fix2(Mesh m, Ctl *ctl, State<R> cur
     }
     __syncthreads();
   }
-  block_max_to_ctl<FW * FH>(ctl, a, bad);
+  block_max_to_ctl<NT4>(ctl, a, bad);
 }
 
 }  // namespace
@@ -565,9 +574,9 @@ hipError_t launch_remap2(const Mesh &m, Ctl *ctl, const Work<R> &w, int cur, hip
   const Grid2 gcell = tiles(m.nx, m.ny, m.nz, CTX, CTY);
   hipLaunchKernelGGL(k_cells2<R>, dim3((unsigned)gcell.blocks()), dim3(NT2), 0, s, m, ctl, sc, sn, w.geo, w.r2,
                      gcell);
-  hipLaunchKernelGGL(k_nodes2<R>, dim3((unsigned)gnode.blocks()), dim3(NW * NH), 0, s, m, ctl, sc, sn, w.geo, w.up,
+  hipLaunchKernelGGL(k_nodes2<R>, dim3((unsigned)gnode.blocks()), dim3(NT3), 0, s, m, ctl, sc, sn, w.geo, w.up,
                      w.vp, w.wp, w.r2, gnode);
-  hipLaunchKernelGGL(k_fix2<R>, dim3((unsigned)gf.blocks()), dim3(FW * FH), 0, s, m, ctl, sc, sn, w.r2, gf);
+  hipLaunchKernelGGL(k_fix2<R>, dim3((unsigned)gf.blocks()), dim3(NT4), 0, s, m, ctl, sc, sn, w.r2, gf);
   return hipGetLastError();
 }
 
