@@ -90,13 +90,19 @@ struct Rem2 {
 
 // Pure-Lagrangian mode (FP64 only; null otherwise): node positions of the two
 // states, the constant cell masses, and the corner forces of the step in
-// flight, F[(3 a + d) * ncell + c] for corner a = (a&1, a>>1&1, a>>2&1) and
-// component d of cell c.
+// flight, F[(3 a + d) * corner_stride(ncell) + c] for corner a = (a&1, a>>1&1,
+// a>>2&1) and component d of cell c.
 struct Lag {
   double *x[2], *y[2], *z[2];
   double *m;
   double *F;
 };
+// Stride in doubles between the 24 corner-force arrays: the cell count
+// rounded up to 256 bytes plus 33 blocks of 256 bytes, so that the arrays do
+// not start at one offset modulo a large power of two (with a power-of-two
+// cell count the 24 streams of a kernel would all meet in the same memory
+// channels).
+__host__ __device__ inline int64_t corner_stride(int64_t ncell) { return (ncell + 31) / 32 * 32 + 33 * 32; }
 
 template <typename R>
 struct Work {

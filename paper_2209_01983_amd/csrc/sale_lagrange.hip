@@ -164,6 +164,7 @@ __global__ __launch_bounds__(TPL) void k_lag_forces(Mesh m, Ctl *ctl, State<doub
   int i, j, k;
   ijk_of(c, m.nx, m.ny, i, j, k);
   const double dt = ctl->dt;
+  const int64_t fs = corner_stride(m.ncell);
   double X[8][3], S[8][3], V;
   load_corners(m, x, y, z, i, j, k, X);
   hex_volume(X, S, V);
@@ -228,7 +229,7 @@ __global__ __launch_bounds__(TPL) void k_lag_forces(Mesh m, Ctl *ctl, State<doub
 #pragma unroll
   for (int a = 0; a < 8; a++)
 #pragma unroll
-    for (int d = 0; d < 3; d++) F[(3 * a + d) * m.ncell + c] = Fc[a][d];
+    for (int d = 0; d < 3; d++) F[(3 * a + d) * fs + c] = Fc[a][d];
 }
 
 __global__ __launch_bounds__(TPL) void k_lag_nodes(Mesh m, Ctl *ctl, State<double> cur, State<double> nxt,
@@ -243,6 +244,7 @@ __global__ __launch_bounds__(TPL) void k_lag_nodes(Mesh m, Ctl *ctl, State<doubl
   }
   int i, j, k;
   ijk_of(n, m.nx + 1, m.ny + 1, i, j, k);
+  const int64_t fs = corner_stride(m.ncell);
   double f[3] = {0.0, 0.0, 0.0}, ms = 0.0;
 #pragma unroll
   for (int a = 0; a < 8; a++) {  // this node is corner a of cell (i, j, k) - bits(a)
@@ -250,7 +252,7 @@ __global__ __launch_bounds__(TPL) void k_lag_nodes(Mesh m, Ctl *ctl, State<doubl
     if (ci < 0 || ci >= m.nx || cj < 0 || cj >= m.ny || ck < 0 || ck >= m.nz) continue;
     const int64_t c = ci + (int64_t)m.nx * (cj + (int64_t)m.ny * ck);
 #pragma unroll
-    for (int d = 0; d < 3; d++) f[d] += F[(3 * a + d) * m.ncell + c];
+    for (int d = 0; d < 3; d++) f[d] += F[(3 * a + d) * fs + c];
     ms += mass[c];
   }
   const double mp = 0.125 * ms, dt = ctl->dt;
@@ -312,13 +314,14 @@ __global__ __launch_bounds__(TPL) void k_lag_energy(Mesh m, Ctl *ctl, State<doub
     int i, j, k;
     ijk_of(c, m.nx, m.ny, i, j, k);
     const double dt = ctl->dt, mc = mass[c];
+    const int64_t fs = corner_stride(m.ncell);
     double work = 0.0;
 #pragma unroll 1
     for (int a = 0; a < 8; a++) {
       const int64_t n = node_at(m, i + (a & 1), j + ((a >> 1) & 1), k + ((a >> 2) & 1));
       const double ub[3] = {0.5 * (cur.u[n] + nxt.u[n]), 0.5 * (cur.v[n] + nxt.v[n]), 0.5 * (cur.w[n] + nxt.w[n])};
 #pragma unroll
-      for (int d = 0; d < 3; d++) work += F[(3 * a + d) * m.ncell + c] * ub[d];
+      for (int d = 0; d < 3; d++) work += F[(3 * a + d) * fs + c] * ub[d];
     }
     const double en = cur.e[c] - dt * work / mc;
     double X[8][3], S[8][3], V;

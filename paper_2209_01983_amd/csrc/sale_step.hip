@@ -413,7 +413,8 @@ size_t inter_bytes(const Mesh &m) {
   // (+ rho^L and the second-order remap's intermediates for order 2)
   const size_t r2 = m.order == 2 ? 6 * cR + nR : 0;
   const size_t cD = align256((size_t)m.ncell * sizeof(double)), nD = align256((size_t)m.nnode * sizeof(double));
-  const size_t lg = m.mode == 1 ? 6 * nD + 25 * cD : 0;  // positions x2, masses, corner forces
+  // positions x2, masses, corner forces
+  const size_t lg = m.mode == 1 ? 6 * nD + cD + align256(24 * (size_t)corner_stride(m.ncell) * sizeof(double)) : 0;
   return 3 * nR + cR + 3 * cR + align256(3 * TOT_BLOCKS * sizeof(double)) + sD + r2 + lg;
 }
 
@@ -474,7 +475,7 @@ void layout_split(const Mesh &m, void *state, void *inter, Ctl **ctl, Work<R> *w
       w->lg.z[a] = takeD(nD);
     }
     w->lg.m = takeD(cD);
-    w->lg.F = takeD(24 * cD);
+    w->lg.F = takeD(align256(24 * (size_t)corner_stride(m.ncell) * sizeof(double)));
   }
 }
 
