@@ -399,10 +399,16 @@ static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 // reduction partials, the scratch array, and the second-order and
 // pure-Lagrangian arrays). A single-run workspace holds both back to back;
 // sale_init_static puts the intermediates in the library's device array.
+// Every array is followed by a gap of 33 blocks of 256 bytes, so that arrays
+// of a power-of-two size do not start at one offset modulo that size (the
+// streams a kernel reads side by side would meet in the same memory
+// channels).
+constexpr size_t kGap = 33 * 256;
+
 template <typename R>
 size_t state_bytes(const Mesh &m) {
   const size_t cR = align256((size_t)m.ncell * sizeof(R)), nR = align256((size_t)m.nnode * sizeof(R));
-  return align256(sizeof(Ctl)) + 2 * (2 * cR + 3 * nR);
+  return align256(sizeof(Ctl)) + 2 * (2 * cR + 3 * nR) + 10 * kGap;
 }
 
 template <typename R>
@@ -415,7 +421,8 @@ size_t inter_bytes(const Mesh &m) {
   const size_t cD = align256((size_t)m.ncell * sizeof(double)), nD = align256((size_t)m.nnode * sizeof(double));
   // positions x2, masses, corner forces
   const size_t lg = m.mode == 1 ? 6 * nD + cD + align256(24 * (size_t)corner_stride(m.ncell) * sizeof(double)) : 0;
-  return 3 * nR + cR + 3 * cR + align256(3 * TOT_BLOCKS * sizeof(double)) + sD + r2 + lg;
+  const size_t arrays = 9 + (m.order == 2 ? 7 : 0) + (m.mode == 1 ? 8 : 0);
+  return 3 * nR + cR + 3 * cR + align256(3 * TOT_BLOCKS * sizeof(double)) + sD + r2 + lg + arrays * kGap;
 }
 
 template <typename R>
@@ -432,12 +439,12 @@ void layout_split(const Mesh &m, void *state, void *inter, Ctl **ctl, Work<R> *w
   p += align256(sizeof(Ctl));
   auto takeR = [&](size_t b) {
     R *r = (R *)p;
-    p += b;
+    p += b + kGap;
     return r;
   };
   auto takeD = [&](size_t b) {
     double *r = (double *)p;
-    p += b;
+    p += b + kGap;
     return r;
   };
   for (int a = 0; a < 2; a++) {
