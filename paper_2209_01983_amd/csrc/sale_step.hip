@@ -402,7 +402,8 @@ static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 // Every array is followed by a gap of 33 blocks of 256 bytes, so that arrays
 // of a power-of-two size do not start at one offset modulo that size (the
 // streams a kernel reads side by side would meet in the same memory
-// channels).
+// channels). At 320^3 in FP64 the gap is worth 1% of the step (gaps of 1 to
+// 129 blocks measure the same).
 constexpr size_t kGap = 33 * 256;
 
 template <typename R>
