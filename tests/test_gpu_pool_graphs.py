@@ -70,3 +70,35 @@ def test_graph_replayed_rounds_are_bitwise_the_launched_rounds(monkeypatch, prec
             assert np.array_equal(f_g[k], f_r[k]), (s, k)
     # the runs reached their step targets
     assert sorted(v[0][1] for v in ref.values()) == [25, 30, 40]
+
+
+def test_pool_destroyed_with_replays_queued(monkeypatch):
+    """Destroying a pool right after an advance, its round graph's replays
+    still queued on the stream, waits for them before the graph goes; pools
+    created afterwards (their arenas may reuse the freed memory) run to
+    bitwise equal results."""
+    say("pool destroy with queued replays")
+    monkeypatch.setenv("SALE_POOL_PERSISTENT", "0")
+    monkeypatch.setenv("SALE_POOL_GRAPHS", "1")
+    n = (40, 24, 30)
+    cfg = sale.make_config(*n, hi=(1.0, 0.6, 0.75), t_end=100.0)
+
+    def run(close_early):
+        pool = sale.Pool(ARENA, max_runs=4)
+        st = random_state(*n, seed=77, smooth=True)
+        p, keep = sale.user_problem(st["rho"], st["e"], st["u"], st["v"], st["w"])
+        s = pool.admit(cfg, p, 40)
+        pool.advance(40)
+        if close_early:
+            pool.close()  # the 39 replays may still be in flight
+            return None
+        pool.poll()
+        out = pool.fields(s)
+        pool.close()
+        return out
+
+    run(True)
+    a = run(False)
+    b = run(False)
+    for k in FIELDS:
+        assert np.array_equal(a[k], b[k]), k
