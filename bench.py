@@ -27,9 +27,10 @@ Also reported (one JSON line, extra keys):
                10 warm-up steps, kernel split (forces+nodes, energy+geometry).
   batched      256 runs (seeded mix of Sod / Sedov, edges 16..64), MIXED32
                and FP64, 200 steps each in ONE pool advance, in three advance
-               modes (one persistent launch; lockstep kernels with the steps
-               after the first replayed from a captured HIP graph; lockstep
-               kernels all launched): aggregate cell-updates/s, makespan,
+               modes (one persistent launch, the library's choice for this
+               workload and the block's headline; lockstep kernels with the
+               steps after the first replayed from a captured HIP graph;
+               lockstep kernels all launched): aggregate cell-updates/s, makespan,
                per-run latency p50/p99; the same runs one after another on the
                plain FP64 path.
   serving      seeded Poisson trace (50 requests/s, cubic 32^3..192^3,
@@ -302,8 +303,9 @@ def batched(seq_fp64=True, modes=None, steps=200):
     modes = [m for m, _ in POOL_MODES] if modes is None else modes
     out = {"workload": f"256 runs, edges 16..64 (seed 2209), 128 sod + 128 sedov, {steps} steps, one pool advance",
            "cells_total": sum(workloads.cells(r) for r in reqs),
-           "modes": {"persistent": "one launch of the persistent kernel per advance (work items pulled from a "
-                                   "device queue, per-run phase waits)",
+           "modes": {"persistent": "one launch of the persistent kernel per advance (each run served by the "
+                                   "blocks of one XCD, work items pulled from per-XCD device queues, per-run "
+                                   "phase waits); the mode the library chooses for this workload",
                      "lockstep": "per step: one kernel each for dt, the Lagrange tiles of all runs, the remap "
                                  "tiles of all runs and the clocks; the first step launched, the other 199 "
                                  "replays of one captured HIP graph of a step",

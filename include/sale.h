@@ -266,21 +266,30 @@ void sale_destroy(sale_ctx *ctx);
 
 /* ---- pool: many independent runs, advanced together ------------------------
  * Batched and served runs: independent runs of different mesh sizes share one
- * caller-owned device arena and are advanced together. By default an advance
- * is a sequence of lockstep rounds: per round one launch computes every run's
- * time step, one launch runs the Lagrange tiles of all runs and one the remap
- * tiles of all runs (each run's z extent split in proportion to its share of
- * the cells), so the kernel boundaries order the phases. With the environment
- * variable SALE_POOL_PERSISTENT=1 at sale_pool_create, an advance is instead
- * one persistent kernel launch that pulls (round, phase, run, tile) work items
- * from a device queue, a run's phase waiting only for that run's previous
- * phase. Each run has its own time step; a run that is done skips its tiles.
- * A run's results do not depend on which other runs share the pool, nor on
- * the advance mode. In the lockstep mode the rounds after an advance's first
- * are replays of one HIP graph of a round's four launches, captured on a
- * stream of the pool's own and kept while the set of active runs and the
- * block counts stay the same (SALE_POOL_GRAPHS=0 at sale_pool_create
- * launches every round instead); the graph holds kernel launches only. */
+ * caller-owned device arena and are advanced together, in one of two modes.
+ * Persistent: an advance is one launch of a persistent kernel that pulls
+ * (round, phase, run, tile) work items from device queues, a run's phase
+ * waiting only for that run's previous phase; every run is served by the
+ * blocks of one XCD (the runs are split into one group per XCD, balanced by
+ * cells), so that a run's tiles meet in that XCD's L2. Lockstep: an advance is
+ * a sequence of rounds; per round one launch computes every run's time step,
+ * one launch runs the Lagrange tiles of all runs and one the remap tiles of
+ * all runs, so the kernel boundaries order the phases; the rounds after an
+ * advance's first are replays of one HIP graph of a round's four launches,
+ * captured on a stream of the pool's own and kept while the set of active
+ * runs and the block counts stay the same (SALE_POOL_GRAPHS=0 at
+ * sale_pool_create launches every round instead); the graph holds kernel
+ * launches only. In both modes each run's z extent is split in proportion to
+ * its share of the cells. The mode is chosen per advance: persistent when
+ * there are at least four active runs per XCD and the busiest XCD's cells are
+ * within 10% of the mean, lockstep otherwise; the environment variable
+ * SALE_POOL_PERSISTENT=1 (=0) at sale_pool_create forces the persistent
+ * (lockstep) mode. Each run has its own time step; a run that is done skips
+ * its tiles. A run's results do not depend on which other runs share the
+ * pool, nor on the advance mode. SALE_POOL_XCC_MASK at sale_pool_create (a
+ * bit mask of XCD ids) replaces the XCDs the device reports for the grouping;
+ * a run assigned to an XCD that receives no block of the persistent launch is
+ * not advanced and is flagged SALE_FLAG_NUMERIC (a test hook). */
 typedef struct sale_pool sale_pool;
 
 /* Create a pool of up to max_runs slots over the device arena
@@ -305,11 +314,13 @@ int sale_pool_admit(sale_pool *pool, const sale_config *cfg, const sale_problem 
                     int32_t *slot);
 
 /* Advance every unfinished admitted run by up to max_steps_per_run steps:
- * lockstep rounds (the first launched, the rest graph replays), or one
- * persistent launch. Synchronises the stream first (the tables of the runs
- * in the advance are copied from host memory), then enqueues the advance and
- * returns without waiting for it. A failed capture or instantiation of the
- * round graph returns SALE_EHIP after the first round was enqueued. */
+ * one persistent launch, or lockstep rounds (the first launched, the rest
+ * graph replays). Synchronises the stream first (the tables of the runs in the
+ * advance are copied from host memory), then enqueues the advance and returns
+ * without waiting for it. The pool's first advance that may take the
+ * persistent mode first runs a small kernel that lists the device's XCD ids
+ * and waits for it. A failed capture or instantiation of the round graph
+ * returns SALE_EHIP after the first round was enqueued. */
 int sale_pool_advance(sale_pool *pool, int32_t max_steps_per_run);
 
 /* Synchronise the stream and list, in done[0..*n_done), the slots whose run

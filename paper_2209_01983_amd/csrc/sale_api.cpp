@@ -599,9 +599,11 @@ struct sale_pool {
   std::vector<std::pair<size_t, size_t>> free_list;  // (offset, size), sorted, disjoint
   std::vector<int> h_act, h_prefA, h_prefB;
   std::vector<Ctl> h_ctl;
-  sale::PoolQueue h_q;
+  sale::PoolQueue h_q = {};
   int resident;
-  bool lockstep;  // advance by lockstep launches (default) or by the persistent kernel
+  // advance mode: 0 chosen per advance, 1 always the persistent kernel, 2
+  // always lockstep launches (SALE_POOL_PERSISTENT unset, 1, 0)
+  int mode = 0;
   // Lockstep rounds after an advance's first are replays of one captured
   // graph of a round (its four launches), kept while the round's shape --
   // active runs and block counts -- stays the same. SALE_POOL_GRAPHS=0 at
@@ -610,6 +612,10 @@ struct sale_pool {
   hipStream_t cap_stream = nullptr;
   hipGraphExec_t round_graph = nullptr;
   int g_nact = -1, g_totA = -1, g_totB = -1;
+  // XCD ids of the device (bit g: XCD g), from a probe launch at the first
+  // persistent advance, or SALE_POOL_XCC_MASK at sale_pool_create
+  unsigned int xcc_mask = 0;
+  bool xcc_known = false;
   ~sale_pool() {
     if (round_graph) {
       (void)hipStreamSynchronize(stream);  // replays of it may still be queued
@@ -714,12 +720,20 @@ int sale_pool_create(int32_t precision, int32_t max_runs, void *d_arena, size_t 
   p->free_list.push_back({hdr, arena_bytes - hdr});
   p->h_ctl.resize(max_runs);
   p->resident = precision == SALE_FP64 ? sale::pool_resident_blocks<double>() : sale::pool_resident_blocks<float>();
-  // SALE_POOL_PERSISTENT=1 selects the persistent-kernel advance (one launch
-  // per advance, device-side phase waits) instead of lockstep launches
+  // SALE_POOL_PERSISTENT=1 / 0: every advance by the persistent kernel / by
+  // lockstep launches; unset: chosen per advance
   const char *pers = getenv("SALE_POOL_PERSISTENT");
-  p->lockstep = !(pers && pers[0] == '1');
+  p->mode = pers && pers[0] == '1' ? 1 : pers && pers[0] == '0' ? 2 : 0;
   const char *gr = getenv("SALE_POOL_GRAPHS");
   p->graphs = !(gr && gr[0] == '0');
+  // SALE_POOL_XCC_MASK: the XCDs the persistent advance assigns runs to,
+  // instead of the probed ones (a test hook: a run on an XCD that serves no
+  // block is flagged, not advanced)
+  const char *xm = getenv("SALE_POOL_XCC_MASK");
+  if (xm && xm[0]) {
+    p->xcc_mask = (unsigned int)strtoul(xm, nullptr, 0) & ((1u << sale::kPoolGroups) - 1u);
+    p->xcc_known = p->xcc_mask != 0;
+  }
   *out = p;
   return SALE_OK;
 }
@@ -802,13 +816,60 @@ int sale_pool_advance(sale_pool *p, int32_t max_steps_per_run) {
   }
   const int nact = (int)p->h_act.size();
   if (nact == 0) return SALE_OK;
+  // The persistent kernel serves each run from the blocks of one XCD: one
+  // group of runs per XCD, balanced by cells (largest first, each to the least
+  // loaded XCD). Chosen per advance: the persistent kernel when there are at
+  // least four runs per XCD and the busiest is within 10% of the mean load, else
+  // lockstep launches (few or uneven runs leave XCDs idle in the persistent
+  // kernel).
+  bool persistent = p->mode == 1;
+  std::vector<int> grp(p->max_runs, -1);
+  if (p->mode != 2) {
+    if (!p->xcc_known) {
+      unsigned int mask = 0;
+      HIP_TRY(hipMemsetAsync(&p->d_q->xcc_mask, 0, sizeof(unsigned int), p->stream));
+      HIP_TRY(sale::launch_xcc_probe(p->d_q, p->stream));
+      HIP_TRY(hipMemcpyAsync(&mask, &p->d_q->xcc_mask, sizeof(unsigned int), hipMemcpyDeviceToHost, p->stream));
+      HIP_TRY(hipStreamSynchronize(p->stream));
+      if (mask == 0) return SALE_EHIP;
+      p->xcc_mask = mask;
+      p->xcc_known = true;
+    }
+    std::vector<int> order = p->h_act;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return p->slots[a].m.ncell > p->slots[b].m.ncell; });
+    double load[sale::kPoolGroups] = {}, total = 0.0;
+    int nx = 0;
+    for (int g = 0; g < sale::kPoolGroups; g++) nx += (int)(p->xcc_mask >> g & 1u);
+    for (int k : order) {
+      int best = -1;
+      for (int g = 0; g < sale::kPoolGroups; g++)
+        if ((p->xcc_mask >> g & 1u) && (best < 0 || load[g] < load[best])) best = g;
+      grp[k] = best;
+      load[best] += (double)p->slots[k].m.ncell;
+      total += (double)p->slots[k].m.ncell;
+    }
+    const double busiest = *std::max_element(load, load + sale::kPoolGroups);
+    if (p->mode == 0) persistent = nact >= 4 * nx && busiest <= 1.1 * total / nx;
+  }
   {
     // z split of each run sized to its share of the advance's cells, about
     // `target` tiles per phase in all (one segment for runs too small, and
     // for every run when the target is 0)
-    const double target = p->lockstep ? 3072.0 : (double)SALE_POOL_PERSISTENT_BLOCKS;
+    const double target = persistent ? (double)SALE_POOL_PERSISTENT_BLOCKS : 3072.0;
     double cells = 0.0;
     for (int k : p->h_act) cells += (double)p->slots[k].m.ncell;
+    if (persistent) {
+      // act lists the XCD groups in XCD order, each in slot order
+      std::vector<int> act;
+      for (int g = 0; g < sale::kPoolGroups; g++) {
+        p->h_q.gact[g] = (int)act.size();
+        for (int k : p->h_act)
+          if (grp[k] == g) act.push_back(k);
+      }
+      p->h_q.gact[sale::kPoolGroups] = (int)act.size();
+      p->h_act = act;
+    }
     p->h_prefA.assign(1, 0);
     p->h_prefB.assign(1, 0);
     for (int k : p->h_act) {
@@ -835,7 +896,7 @@ int sale_pool_advance(sale_pool *p, int32_t max_steps_per_run) {
   HIP_TRY(hipMemcpyAsync(p->d_act, p->h_act.data(), nact * sizeof(int), hipMemcpyHostToDevice, p->stream));
   HIP_TRY(hipMemcpyAsync(p->d_prefA, p->h_prefA.data(), (nact + 1) * sizeof(int), hipMemcpyHostToDevice, p->stream));
   HIP_TRY(hipMemcpyAsync(p->d_prefB, p->h_prefB.data(), (nact + 1) * sizeof(int), hipMemcpyHostToDevice, p->stream));
-  if (p->lockstep) {
+  if (!persistent) {
     auto rounds = [&](int n, int first, hipStream_t s) {
       return p->precision == SALE_FP64
                  ? sale::launch_pool_lockstep<double>((const sale::PoolRun<double> *)p->d_runs, p->d_act,
@@ -870,15 +931,19 @@ int sale_pool_advance(sale_pool *p, int32_t max_steps_per_run) {
     for (int r = 1; r < max_steps_per_run; r++) HIP_TRY(hipGraphLaunch(p->round_graph, p->stream));
     return SALE_OK;
   }
-  p->h_q.head = 0;
+  for (int g = 0; g < sale::kPoolGroups; g++) p->h_q.head[g] = 0;
   p->h_q.nact = nact;
   p->h_q.rounds = max_steps_per_run;
   p->h_q.totA = totA;
   p->h_q.totB = totB;
   p->h_q.timeouts = 0;
   p->h_q.abort = 0;
-  const unsigned long long items = (unsigned long long)(totA + totB) * (unsigned long long)max_steps_per_run;
-  const int blocks = (int)std::min<unsigned long long>((unsigned long long)p->resident, items);
+  p->h_q.exited = 0;
+  p->h_q.starved = 0;
+  p->h_q.xcc_mask = p->xcc_mask;
+  // every resident block, so that every XCD receives blocks (a block whose
+  // XCD serves no run leaves at once)
+  const int blocks = p->resident;
   HIP_TRY(hipMemcpyAsync(p->d_q, &p->h_q, sizeof(p->h_q), hipMemcpyHostToDevice, p->stream));
   if (p->precision == SALE_FP64)
     HIP_TRY(sale::launch_pool_advance<double>((sale::PoolRun<double> *)p->d_runs, p->d_act, p->d_prefA, p->d_prefB,

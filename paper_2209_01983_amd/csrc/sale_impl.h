@@ -232,14 +232,22 @@ struct PoolRun {
   long long step_target;
 };
 
+// XCD queues of the persistent advance: every run is served by the blocks
+// of one XCD (the ids the hardware reports fit in 4 bits).
+constexpr int kPoolGroups = 16;
+
 // Queue header and the active-run tables of one advance.
 struct PoolQueue {
-  unsigned long long head;  // next item to hand out
-  int nact;                 // active runs in this advance
-  int rounds;               // steps per run in this advance
-  int totA, totB;           // Lagrange / remap tiles over all active runs
-  unsigned int timeouts;    // waits that hit the time cap
-  unsigned int abort;       // set by a timed-out wait: later waits give up at once
+  unsigned long long head[kPoolGroups];  // next item of each XCD's queue
+  int nact;                              // active runs in this advance
+  int rounds;                            // steps per run in this advance
+  int totA, totB;                        // Lagrange / remap tiles over all active runs
+  int gact[kPoolGroups + 1];             // XCD g serves the runs act[gact[g] .. gact[g+1])
+  unsigned int timeouts;                 // waits that hit the time cap
+  unsigned int abort;                    // set by a timed-out wait: later waits give up at once
+  unsigned int exited;                   // blocks that have left the item loop
+  unsigned int starved;                  // queues with runs that no block served
+  unsigned int xcc_mask;                 // XCD ids seen by the probe
 };
 
 // Tile shape of the multi-run kernels: kPoolWidth x kPoolRows columns (their
@@ -249,14 +257,15 @@ struct PoolQueue {
 #endif
 constexpr int kPoolRows = SALE_POOL_ROWS, kPoolWidth = 32;
 // Tiles per phase the persistent advance splits the runs' z extents into, in
-// proportion to their cells (0: one z segment per tile column). The lockstep
-// advance aims at 3072 blocks per launch.
+// proportion to their cells (0: one z segment per tile column); about two per
+// resident block. The lockstep advance aims at 3072 blocks per launch.
 #ifndef SALE_POOL_PERSISTENT_BLOCKS
-#define SALE_POOL_PERSISTENT_BLOCKS 0
+#define SALE_POOL_PERSISTENT_BLOCKS 1024
 #endif
 
-// Persistent multi-run advance: prepare (queue head, per-run counters, first
-// dt) and the persistent kernel over `blocks` blocks; tables on the device.
+// Persistent multi-run advance: prepare (queue heads, per-run counters, first
+// dt) and the persistent kernel over `blocks` blocks; tables on the device
+// (act grouped by XCD as qh->gact says).
 template <typename R>
 hipError_t launch_pool_advance(PoolRun<R> *runs, const int *act, const int *prefA, const int *prefB,
                                PoolQueue *qh, int nact, int blocks, hipStream_t s);
@@ -271,5 +280,8 @@ hipError_t launch_pool_lockstep(const PoolRun<R> *runs, const int *act, const in
 // Blocks of the persistent kernel that fit on the device at once.
 template <typename R>
 int pool_resident_blocks();
+// OR of 1 << (XCD id) over the blocks of a wide launch into qh->xcc_mask
+// (which the caller clears first).
+hipError_t launch_xcc_probe(PoolQueue *qh, hipStream_t s);
 
 }  // namespace sale

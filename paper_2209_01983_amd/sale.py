@@ -393,8 +393,9 @@ class SaleRun:
 
 class Pool:
     """Many independent runs in one device arena (a torch uint8 tensor of
-    `arena_bytes` on `device`), advanced together by the library's persistent
-    kernel on torch's current stream."""
+    `arena_bytes` on `device`), advanced together on torch's current stream
+    (the library's persistent kernel or lockstep launches, chosen per advance
+    unless SALE_POOL_PERSISTENT forces one)."""
 
     def __init__(self, arena_bytes, max_runs=256, precision=SALE_FP64, device="cuda:0"):
         import torch

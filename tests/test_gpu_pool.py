@@ -1,6 +1,7 @@
 """GPU tests of the pool: many independent runs advanced together, through
 the C ABI, in both advance modes (lockstep launches over all runs, and the
-persistent multi-run kernel).
+persistent multi-run kernel serving each run from one XCD) and with the mode
+chosen per advance.
 
 Bars: every pool run matches the FP64 oracle run of the same problem and step
 count to 1e-12 per field (the single-run bar); a run's results are bitwise
@@ -25,10 +26,15 @@ pytestmark = pytest.mark.gpu
 ARENA = 256 << 20
 
 
-@pytest.fixture(autouse=True, params=["lockstep", "persistent"])
+@pytest.fixture(autouse=True, params=["lockstep", "persistent", "auto"])
 def advance_mode(request, monkeypatch):
-    """Every pool test runs with both advance modes (read at pool creation)."""
-    monkeypatch.setenv("SALE_POOL_PERSISTENT", "1" if request.param == "persistent" else "0")
+    """Every pool test runs with both advance modes forced and with the mode
+    chosen per advance (read at pool creation)."""
+    if request.param == "auto":
+        monkeypatch.delenv("SALE_POOL_PERSISTENT", raising=False)
+    else:
+        monkeypatch.setenv("SALE_POOL_PERSISTENT", "1" if request.param == "persistent" else "0")
+    monkeypatch.delenv("SALE_POOL_XCC_MASK", raising=False)
     return request.param
 
 
