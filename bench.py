@@ -26,11 +26,11 @@ Also reported (one JSON line, extra keys):
                128^3, FP64: per-step throughput over a 100-step window after
                10 warm-up steps, kernel split (forces+nodes, energy+geometry).
   batched      256 runs (seeded mix of Sod / Sedov, edges 16..64), MIXED32
-               and FP64, 200 steps each in ONE pool advance, in three advance
-               modes (one persistent launch, the library's choice for this
-               workload and the block's headline; lockstep kernels with the
-               steps after the first replayed from a captured HIP graph;
-               lockstep kernels all launched): aggregate cell-updates/s, makespan,
+               and FP64, 200 steps each in ONE pool advance, in four advance
+               modes (one persistent launch, the block's headline; lockstep
+               kernels with the steps after the first replayed from a captured
+               HIP graph; lockstep kernels all launched; no mode forced, the
+               library's choice): aggregate cell-updates/s, makespan,
                per-run latency p50/p99; the same runs one after another on the
                plain FP64 path.
   serving      seeded Poisson trace (50 requests/s, cubic 32^3..192^3,
@@ -82,6 +82,8 @@ def parse():
     ap.add_argument("--pool-modes", default=",".join(m for m, _ in POOL_MODES),
                     help="batched block: the pool advance modes to run (comma list)")
     ap.add_argument("--batched-steps", type=int, default=200, help="batched block: steps per run")
+    ap.add_argument("--batch-runs", type=int, default=256, help="batched block (--section batched): runs")
+    ap.add_argument("--batch-edge", default="16,64", help="batched block (--section batched): mesh edges lo,hi")
     ap.add_argument("--no-seq", action="store_true",
                     help="batched block: skip the sequential single-run FP64 comparison")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -279,37 +281,45 @@ def _with_pool_mode(env, fn):
     (the library reads SALE_POOL_PERSISTENT and SALE_POOL_GRAPHS when a pool
     is created)."""
     old = {k: os.environ.get(k) for k in env}
-    os.environ.update(env)
+    for k, v in env.items():
+        if v is None:
+            os.environ.pop(k, None)
+        else:
+            os.environ[k] = v
     try:
         return fn()
     finally:
         for k, v in old.items():
             if v is None:
-                del os.environ[k]
+                os.environ.pop(k, None)
             else:
                 os.environ[k] = v
 
 
 POOL_MODES = (("persistent", {"SALE_POOL_PERSISTENT": "1"}),
               ("lockstep", {"SALE_POOL_PERSISTENT": "0", "SALE_POOL_GRAPHS": "1"}),
-              ("lockstep_launched", {"SALE_POOL_PERSISTENT": "0", "SALE_POOL_GRAPHS": "0"}))
+              ("lockstep_launched", {"SALE_POOL_PERSISTENT": "0", "SALE_POOL_GRAPHS": "0"}),
+              ("default", {"SALE_POOL_PERSISTENT": None, "SALE_POOL_GRAPHS": None}))
 
 
-def batched(seq_fp64=True, modes=None, steps=200):
+def batched(seq_fp64=True, modes=None, steps=200, runs=256, edge=(16, 64)):
     from paper_2209_01983_amd import sale, workloads
     from paper_2209_01983_amd.inputs import BATCH_SEED, batch_mix
 
-    reqs = batch_mix(256, seed=BATCH_SEED)
+    reqs = batch_mix(runs, seed=BATCH_SEED, edge=edge)
     modes = [m for m, _ in POOL_MODES] if modes is None else modes
-    out = {"workload": f"256 runs, edges 16..64 (seed 2209), 128 sod + 128 sedov, {steps} steps, one pool advance",
+    out = {"workload": f"{runs} runs, edges {edge[0]}..{edge[1]} (seed 2209), {runs // 2} sod + {runs - runs // 2} "
+                       f"sedov, {steps} steps, one pool advance",
            "cells_total": sum(workloads.cells(r) for r in reqs),
            "modes": {"persistent": "one launch of the persistent kernel per advance (each run served by the "
                                    "blocks of one XCD, work items pulled from per-XCD device queues, per-run "
-                                   "phase waits); the mode the library chooses for this workload",
+                                   "phase waits)",
                      "lockstep": "per step: one kernel each for dt, the Lagrange tiles of all runs, the remap "
-                                 "tiles of all runs and the clocks; the first step launched, the other 199 "
+                                 f"tiles of all runs and the clocks; the first step launched, the other {steps - 1} "
                                  "replays of one captured HIP graph of a step",
-                     "lockstep_launched": "the lockstep kernels, every step launched (no graph)"}}
+                     "lockstep_launched": "the lockstep kernels, every step launched (no graph)",
+                     "default": "no mode forced: the library's choice (persistent with at least four runs per "
+                                "XCD and balanced XCD loads, lockstep launched otherwise)"}}
     for mode, env in POOL_MODES:
         if mode not in modes:
             continue
@@ -508,7 +518,8 @@ def main():
     if a.section:
         block = {"latency": lambda: sod_latency(50), "sedov128": lambda: sedov128(3), "noh128": lambda: noh128(3),
                  "lagrange128": lagrange128,
-                 "batched": lambda: batched(not a.no_seq, a.pool_modes.split(","), a.batched_steps),
+                 "batched": lambda: batched(not a.no_seq, a.pool_modes.split(","), a.batched_steps, a.batch_runs,
+                                            tuple(int(x) for x in a.batch_edge.split(","))),
                  "serving": lambda: serving(a.serve_requests, a.serve_budget_gb)}[a.section]
         print(json.dumps({a.section: block()}), flush=True)
         return

@@ -274,12 +274,13 @@ void sale_destroy(sale_ctx *ctx);
  * cells), so that a run's tiles meet in that XCD's L2. Lockstep: an advance is
  * a sequence of rounds; per round one launch computes every run's time step,
  * one launch runs the Lagrange tiles of all runs and one the remap tiles of
- * all runs, so the kernel boundaries order the phases; the rounds after an
+ * all runs, so the kernel boundaries order the phases. With the environment
+ * variable SALE_POOL_GRAPHS=1 at sale_pool_create, the rounds after an
  * advance's first are replays of one HIP graph of a round's four launches,
  * captured on a stream of the pool's own and kept while the set of active
- * runs and the block counts stay the same (SALE_POOL_GRAPHS=0 at
- * sale_pool_create launches every round instead); the graph holds kernel
- * launches only. In both modes each run's z extent is split in proportion to
+ * runs and the block counts stay the same (the graph holds kernel launches
+ * only); by default every round is launched (as fast or faster on the pools
+ * measured). In both modes each run's z extent is split in proportion to
  * its share of the cells. The mode is chosen per advance: persistent when
  * there are at least four active runs per XCD and the busiest XCD's cells are
  * within 10% of the mean, lockstep otherwise; the environment variable
@@ -314,13 +315,13 @@ int sale_pool_admit(sale_pool *pool, const sale_config *cfg, const sale_problem 
                     int32_t *slot);
 
 /* Advance every unfinished admitted run by up to max_steps_per_run steps:
- * one persistent launch, or lockstep rounds (the first launched, the rest
- * graph replays). Synchronises the stream first (the tables of the runs in the
- * advance are copied from host memory), then enqueues the advance and returns
- * without waiting for it. The pool's first advance that may take the
- * persistent mode first runs a small kernel that lists the device's XCD ids
- * and waits for it. A failed capture or instantiation of the round graph
- * returns SALE_EHIP after the first round was enqueued. */
+ * one persistent launch, or lockstep rounds (launched, or the first launched
+ * and the rest graph replays). Synchronises the stream first (the tables of
+ * the runs in the advance are copied from host memory), then enqueues the
+ * advance and returns without waiting for it. The pool's first advance that
+ * may take the persistent mode first runs a small kernel that lists the
+ * device's XCD ids and waits for it. A failed capture or instantiation of the
+ * round graph returns SALE_EHIP after the first round was enqueued. */
 int sale_pool_advance(sale_pool *pool, int32_t max_steps_per_run);
 
 /* Synchronise the stream and list, in done[0..*n_done), the slots whose run

@@ -604,11 +604,11 @@ struct sale_pool {
   // advance mode: 0 chosen per advance, 1 always the persistent kernel, 2
   // always lockstep launches (SALE_POOL_PERSISTENT unset, 1, 0)
   int mode = 0;
-  // Lockstep rounds after an advance's first are replays of one captured
-  // graph of a round (its four launches), kept while the round's shape --
-  // active runs and block counts -- stays the same. SALE_POOL_GRAPHS=0 at
-  // creation launches every round instead.
-  bool graphs = true;
+  // With SALE_POOL_GRAPHS=1 at creation, lockstep rounds after an advance's
+  // first are replays of one captured graph of a round (its four launches),
+  // kept while the round's shape -- active runs and block counts -- stays
+  // the same; by default every round is launched.
+  bool graphs = false;
   hipStream_t cap_stream = nullptr;
   hipGraphExec_t round_graph = nullptr;
   int g_nact = -1, g_totA = -1, g_totB = -1;
@@ -725,7 +725,7 @@ int sale_pool_create(int32_t precision, int32_t max_runs, void *d_arena, size_t 
   const char *pers = getenv("SALE_POOL_PERSISTENT");
   p->mode = pers && pers[0] == '1' ? 1 : pers && pers[0] == '0' ? 2 : 0;
   const char *gr = getenv("SALE_POOL_GRAPHS");
-  p->graphs = !(gr && gr[0] == '0');
+  p->graphs = gr && gr[0] == '1';
   // SALE_POOL_XCC_MASK: the XCDs the persistent advance assigns runs to,
   // instead of the probed ones (a test hook: a run on an XCD that serves no
   // block is flagged, not advanced)
