@@ -37,8 +37,7 @@
 #include "sale_tiles.h"
 
 // waves per SIMD the persistent kernel is compiled for: 4 (two 512-thread
-// blocks per CU); each tile kind is a call of its own, so the kernel needs the
-// registers of the larger one, not of both
+// blocks per CU, 128 VGPRs)
 #ifndef SALE_WAVES_POOL
 #define SALE_WAVES_POOL 4
 #endif
@@ -134,12 +133,11 @@ __device__ __forceinline__ int cur_of(const PoolRun<R> &p) {
   return (int)((p.ctl->step - 1 - p.step0) & 1);
 }
 
-// One work item of the persistent kernel. Each tile kind is a function of its
-// own (not inlined), so that the kernel's register budget is the larger
-// tile's, not the two tiles' together with the queue loop's; the arguments
-// arrive in vector registers and are made scalar again here.
+// One work item of the persistent kernel. The run descriptor is read into
+// scalar registers (it arrives through a vector pointer), so the tiles
+// address their loads from scalar registers as in the lockstep kernels.
 template <typename R>
-__device__ __attribute__((noinline)) void pool_lagrange_item(const PoolRun<R> *pp, int tile) {
+__device__ __forceinline__ void lagrange_item(const PoolRun<R> *pp, int tile) {
   const PoolRun<R> p = uniform_copy(uniform_ptr(pp));
   const RunArgs<R> a = args_of<R, true>(p, __builtin_amdgcn_readfirstlane(cur_of(p)));
   if (lagrange_tile<R, CH, CW, NT>(a, __builtin_amdgcn_readfirstlane(tile), p.ctl->dt, pool_lds))
@@ -147,7 +145,7 @@ __device__ __attribute__((noinline)) void pool_lagrange_item(const PoolRun<R> *p
 }
 
 template <typename R>
-__device__ __attribute__((noinline)) void pool_remap_item(const PoolRun<R> *pp, int tile) {
+__device__ __forceinline__ void remap_item(const PoolRun<R> *pp, int tile) {
   const PoolRun<R> p = uniform_copy(uniform_ptr(pp));
   const RunArgs<R> a = args_of<R, true>(p, __builtin_amdgcn_readfirstlane(cur_of(p)));
   double amax;
@@ -156,6 +154,24 @@ __device__ __attribute__((noinline)) void pool_remap_item(const PoolRun<R> *pp, 
   block_max_to_ctl<NT>(p.ctl, amax, bad);
   if (tangle) atomicOr(&p.ctl->status, SALE_FLAG_TANGLE);
 }
+
+// The same items as calls of their own (not inlined). Both ways fit the
+// kernel in 128 VGPRs (two blocks per CU). Inlined, the tile loops run a few
+// percent more instructions per plane; called, every item stores and reloads
+// the callee-saved registers (about 12 KB per wave). The FP32-bulk kernel is
+// bound by instruction issue and takes the calls (256 runs: 1.79e10 against
+// 1.70e10 cell-updates/s inlined); the FP64 kernel inlines (32 runs: 8.5e9
+// against 7.8e9 with calls; 256 runs: equal).
+template <typename R>
+__device__ __attribute__((noinline)) void lagrange_item_call(const PoolRun<R> *pp, int tile) {
+  lagrange_item<R>(pp, tile);
+}
+template <typename R>
+__device__ __attribute__((noinline)) void remap_item_call(const PoolRun<R> *pp, int tile) {
+  remap_item<R>(pp, tile);
+}
+template <typename R>
+constexpr bool pool_calls() { return sizeof(R) == 4; }
 
 // The next time step of a pool run, taken inside the persistent kernel by the
 // last tile of its remap phase: begin_step's arithmetic, with the status
@@ -274,10 +290,17 @@ __global__ __launch_bounds__(NT, SALE_WAVES_POOL) void k_pool(const PoolRun<R> *
     __syncthreads();
     const bool ran = s_go && !ctl->done;
     if (ran) {
-      if (!remap)
-        pool_lagrange_item<R>(&p, tile);
-      else
-        pool_remap_item<R>(&p, tile);
+      if (pool_calls<R>()) {
+        if (!remap)
+          lagrange_item_call<R>(&p, tile);
+        else
+          remap_item_call<R>(&p, tile);
+      } else {
+        if (!remap)
+          lagrange_item<R>(&p, tile);
+        else
+          remap_item<R>(&p, tile);
+      }
     }
     // finish the item: its writes reach the XCD's L2, then it is counted; the
     // last tile of the phase opens the next phase (after a remap phase: the
