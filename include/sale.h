@@ -287,10 +287,15 @@ void sale_destroy(sale_ctx *ctx);
  * SALE_POOL_PERSISTENT=1 (=0) at sale_pool_create forces the persistent
  * (lockstep) mode. Each run has its own time step; a run that is done skips
  * its tiles. A run's results do not depend on which other runs share the
- * pool, nor on the advance mode. SALE_POOL_XCC_MASK at sale_pool_create (a
- * bit mask of XCD ids) replaces the XCDs the device reports for the grouping;
- * a run assigned to an XCD that receives no block of the persistent launch is
- * not advanced and is flagged SALE_FLAG_NUMERIC (a test hook). */
+ * pool, nor on the advance mode. In the persistent mode a wait for a run's
+ * previous phase is capped (2 s); a wait that hits the cap aborts the
+ * advance: every later wait gives up at once, and each run with an item that
+ * could not wait is flagged SALE_FLAG_NUMERIC (its state is not trusted).
+ * Test hooks, read at sale_pool_create: SALE_POOL_WAIT_TICKS sets the cap in
+ * ticks of the 100 MHz device clock; SALE_POOL_XCC_MASK (a bit mask of XCD
+ * ids) replaces the XCDs the device reports for the grouping, and a run
+ * assigned to an XCD that receives no block of the persistent launch is not
+ * advanced and is flagged SALE_FLAG_NUMERIC. */
 typedef struct sale_pool sale_pool;
 
 /* Create a pool of up to max_runs slots over the device arena

@@ -616,6 +616,9 @@ struct sale_pool {
   // persistent advance, or SALE_POOL_XCC_MASK at sale_pool_create
   unsigned int xcc_mask = 0;
   bool xcc_known = false;
+  // cap of one wait of the persistent kernel, in ticks of the 100 MHz device
+  // clock (2 s; SALE_POOL_WAIT_TICKS at creation, a test hook)
+  long long wait_ticks = 200000000ll;
   ~sale_pool() {
     if (round_graph) {
       (void)hipStreamSynchronize(stream);  // replays of it may still be queued
@@ -729,6 +732,8 @@ int sale_pool_create(int32_t precision, int32_t max_runs, void *d_arena, size_t 
   // SALE_POOL_XCC_MASK: the XCDs the persistent advance assigns runs to,
   // instead of the probed ones (a test hook: a run on an XCD that serves no
   // block is flagged, not advanced)
+  const char *wt = getenv("SALE_POOL_WAIT_TICKS");
+  if (wt && wt[0]) p->wait_ticks = std::max(0ll, strtoll(wt, nullptr, 0));
   const char *xm = getenv("SALE_POOL_XCC_MASK");
   if (xm && xm[0]) {
     p->xcc_mask = (unsigned int)strtoul(xm, nullptr, 0) & ((1u << sale::kPoolGroups) - 1u);
@@ -936,6 +941,7 @@ int sale_pool_advance(sale_pool *p, int32_t max_steps_per_run) {
   p->h_q.rounds = max_steps_per_run;
   p->h_q.totA = totA;
   p->h_q.totB = totB;
+  p->h_q.wait_ticks = p->wait_ticks;
   p->h_q.timeouts = 0;
   p->h_q.abort = 0;
   p->h_q.exited = 0;

@@ -243,6 +243,7 @@ struct PoolQueue {
   int rounds;                            // steps per run in this advance
   int totA, totB;                        // Lagrange / remap tiles over all active runs
   int gact[kPoolGroups + 1];             // XCD g serves the runs act[gact[g] .. gact[g+1])
+  long long wait_ticks;                  // cap of one wait (100 MHz clock ticks)
   unsigned int timeouts;                 // waits that hit the time cap
   unsigned int abort;                    // set by a timed-out wait: later waits give up at once
   unsigned int exited;                   // blocks that have left the item loop

@@ -58,9 +58,6 @@ constexpr int LDS_L = lagrange_lds_doubles<CH, CW, NT>();
 template <typename R>
 constexpr int LDS_R = remap_lds_doubles<R, CH, CW, NT>();
 constexpr int LDS_DOUBLES = LDS_L > LDS_R<double> ? LDS_L : LDS_R<double>;
-// Cap of one wait, in ticks of the 100 MHz constant clock. A wait normally
-// lasts at most one tile of the same run (milliseconds).
-constexpr long long kWaitTicks = 200000000ll;  // 2 s
 
 // the tile planes of the persistent kernel (both tile kinds)
 __shared__ double pool_lds[LDS_DOUBLES];
@@ -248,6 +245,7 @@ __global__ __launch_bounds__(NT, SALE_WAVES_POOL) void k_pool(const PoolRun<R> *
   const int nA = prefA[a1] - baseA;
   const unsigned long long per_round = (unsigned long long)(nA + prefB[a1] - baseB);
   const int rounds = qh->rounds;
+  const long long wait_ticks = qh->wait_ticks;
   const unsigned long long total = per_round * (unsigned long long)rounds;
   for (;;) {
     __syncthreads();  // the previous item's LDS reads are done
@@ -275,7 +273,7 @@ __global__ __launch_bounds__(NT, SALE_WAVES_POOL) void k_pool(const PoolRun<R> *
           break;
         }
         __builtin_amdgcn_s_sleep(2);
-        if (wall_clock64() - t0 > kWaitTicks) {
+        if (wall_clock64() - t0 > wait_ticks) {
           go = 0;
           atomicAdd(&qh->timeouts, 1u);
           atomicOr(&qh->abort, 1u);

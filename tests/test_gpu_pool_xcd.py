@@ -100,3 +100,25 @@ def test_default_mode_on_many_runs_matches_lockstep(monkeypatch):
         assert ref[s][0][3] == 0 and got[s][0] == ref[s][0], s
         for k in FIELDS:
             assert np.array_equal(got[s][1][k], ref[s][1][k]), (s, k)
+
+
+def test_capped_waits_abort_the_advance_and_flag_their_runs(monkeypatch):
+    """A wait cap of 0 ticks (set from the host) makes the first wait that is
+    not satisfied at once time out: the advance aborts, later waits give up,
+    the runs whose items could not wait are flagged SALE_FLAG_NUMERIC, and
+    the launch ends normally. A run left unflagged completed every step of
+    the advance and matches the same run in a pool without the cap bitwise."""
+    say("pool xcd: capped waits abort the advance")
+    ref, _ = run_pool(monkeypatch, None)
+    monkeypatch.setenv("SALE_POOL_WAIT_TICKS", "0")
+    got, done = run_pool(monkeypatch, None)
+    monkeypatch.delenv("SALE_POOL_WAIT_TICKS")
+    assert sorted(done) == sorted(got)
+    flagged = [s for s, (st, _) in got.items() if st[3] & sale.SALE_FLAG_NUMERIC]
+    assert flagged, "no wait hit a cap of 0 ticks"
+    for s, (st, f) in got.items():
+        if s in flagged:
+            continue
+        assert st == ref[s][0], (s, st, ref[s][0])
+        for k in FIELDS:
+            assert np.array_equal(f[k], ref[s][1][k]), (s, k)
