@@ -13,6 +13,7 @@
 
 #include "../../include/sale.h"
 #include "sale_impl.h"
+#include "sale_pool.h"
 
 using sale::Ctl;
 using sale::Mesh;

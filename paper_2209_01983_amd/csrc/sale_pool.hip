@@ -34,6 +34,7 @@
 //
 // A run's current state buffer follows its own step count, so a run that is
 // done (step target or t_end reached, or flagged) simply skips its items.
+#include "sale_pool.h"
 #include "sale_tiles.h"
 
 // waves per SIMD the persistent kernel is compiled for: 4 (two 512-thread
