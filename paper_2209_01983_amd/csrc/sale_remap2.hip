@@ -215,7 +215,9 @@ __global__ __launch_bounds__(NT2) void k_cells2(Mesh m, Ctl *ctl, State<R> cur, 
 // planes), the z faces' lower + upper sums of plane k (those of plane k-1
 // are carried in registers, formed in the previous pass). u' of node planes
 // k-2..k+2 (the z profiles) is carried in registers. Each input value is
-// read from memory once per tile.
+// read from memory once per tile, and each dual edge's flux is evaluated once
+// (by its lower node; the in-plane ones are handed to the upper node through
+// LDS, the z one to the next plane in registers).
 // (36 x 14 tiles owning 32 x 10 nodes ran slower here: 1.32 -> 1.44 ms at
 // 320^3; the node arrays' rows do not start on 128-byte lines anyway)
 constexpr int NW = 32, NH = 16;
@@ -304,7 +306,7 @@ __global__ __launch_bounds__(NT3, 4) void k_nodes2(Mesh m, Ctl *ctl, State<R> cu
 
   // the z dual faces below node plane k (those of cell plane k-1), carried
   // from the previous pass
-  R zs_m = R(0), zs_v = R(0);
+  R zl[4] = {R(0), R(0), R(0), R(0)};
   for (int k = K0; k < NZ1; k++) {
     R(*const C)[NHL][NW] = LC;
     LU[0][cj][ci] = zu[2];
@@ -338,114 +340,127 @@ __global__ __launch_bounds__(NT3, 4) void k_nodes2(Mesh m, Ctl *ctl, State<R> cu
     };
     // the z dual faces above node plane k: those of the 4 cells of plane k
     const R za_m = own ? R(0.125) * c4(C, SZ) : R(0), za_v = own ? R(0.125) * c4(C, VZ) : R(0);
-    if (own && k >= Z0) {
-      // x edges: cells (i, j-1..j) (outflow) and (i-1, j-1..j) (inflow), lower + upper face each
-      auto xo = [&](R(*P)[NHL][NW], int s) {
-        return (P[s][cj - 1][ci] + P[s][cj - 1][ci + 1]) + (P[s][cj][ci] + P[s][cj][ci + 1]);
-      };
-      auto xi = [&](R(*P)[NHL][NW], int s) {
-        return (P[s][cj - 1][ci - 1] + P[s][cj - 1][ci]) + (P[s][cj][ci - 1] + P[s][cj][ci]);
-      };
-      // y edges: cells (i-1..i, j) (outflow) and (i-1..i, j-1) (inflow)
-      auto yo = [&](R(*P)[NHL][NW], int s) {
-        return (P[s][cj][ci - 1] + P[s][cj + 1][ci - 1]) + (P[s][cj][ci] + P[s][cj + 1][ci]);
-      };
-      auto yi = [&](R(*P)[NHL][NW], int s) {
-        return (P[s][cj - 1][ci - 1] + P[s][cj][ci - 1]) + (P[s][cj - 1][ci] + P[s][cj][ci]);
-      };
-      {
-        const R mp = R(0.125) * (c4(C, MO)), mn = R(0.125) * (c4(C, MN));
-        const R u1 = zu[2], v1 = zv[2], w1 = zw[2];
-        R P0 = mp * u1, P1 = mp * v1, P2 = mp * w1;
-        R K = R(0.5) * mp * (u1 * u1 + v1 * v1 + w1 * w1);
-        auto flow = [&](R phi, R ud, R vd, R wd, R sgn) {
-          P0 += sgn * (phi * ud);
-          P1 += sgn * (phi * vd);
-          P2 += sgn * (phi * wd);
-          K += sgn * (phi * R(0.5) * (ud * ud + vd * vd + wd * wd));
-        };
-        // donor value of one component: limited linear profile of the donor
-        // (values qm, q0, qp at the donor and its two neighbours along the edge)
-        auto recon = [&](R qm, R q0, R qp, bool both, R wgt, bool plus) {
-          return both ? donor_value(q0, vanleer(q0 - qm, qp - q0), wgt, plus) : q0;
-        };
-        // in-plane edge along x (dx = 1, dy = 0) or y (dx = 0, dy = 1) from
-        // LDS column/row `lo` (the lower node) to lo + 1, global index glo
-        auto inplane = [&](int ax, int nlim, int glo, R phi, R dv, R sgn) {
-          const bool lower = phi > R(0);
-          const int dg = lower ? glo : glo + 1;
-          const bool both = dg >= 1 && dg + 1 <= nlim;
-          const R wgt = donor_weight(dv, ihA[ax]);
-          const bool plus = lower && dv != R(0);
-          const int dx = ax == 0, dy = ax == 1;
-          const int x0 = ci + (ax == 0 ? dg - gi : 0), y0 = cj + (ax == 1 ? dg - gj : 0);
-          const R ud = recon(LU[0][y0 - dy][x0 - dx], LU[0][y0][x0], LU[0][y0 + dy][x0 + dx], both, wgt, plus);
-          const R vd = recon(LU[1][y0 - dy][x0 - dx], LU[1][y0][x0], LU[1][y0 + dy][x0 + dx], both, wgt, plus);
-          const R wd = recon(LU[2][y0 - dy][x0 - dx], LU[2][y0][x0], LU[2][y0 + dy][x0 + dx], both, wgt, plus);
-          flow(phi, ud, vd, wd, sgn);
-        };
-        if (gi + 1 <= m.nx)
-          inplane(0, m.nx, gi, R(0.125) * (xo(C, MX)), R(0.125) * (xo(C, VX)), R(-1));
-        if (gi >= 1)
-          inplane(0, m.nx, gi - 1, R(0.125) * (xi(C, MX)), R(0.125) * (xi(C, VX)), R(1));
-        if (gj + 1 <= m.ny)
-          inplane(1, m.ny, gj, R(0.125) * (yo(C, MY)), R(0.125) * (yo(C, VY)), R(-1));
-        if (gj >= 1)
-          inplane(1, m.ny, gj - 1, R(0.125) * (yi(C, MY)), R(0.125) * (yi(C, VY)), R(1));
-        // z edges: the column's own u' at node planes k-2..k+2 (window slot 2 = plane k)
-        auto zedge = [&](int s, R phi, R dv, R sgn) {  // lower node in window slot s
-          const bool lower = phi > R(0);
-          const int d = lower ? s : s + 1;   // donor's window slot
-          const int dg = k - 2 + d;          // donor's node plane
-          const bool both = dg >= 1 && dg + 1 <= m.nz;
-          const R wgt = donor_weight(dv, ihA[2]);
-          const bool plus = lower && dv != R(0);
-          R ud, vd, wd;
-          if (lower && s == 2) {  // donor plane k
-            ud = recon(zu[1], zu[2], zu[3], both, wgt, plus);
-            vd = recon(zv[1], zv[2], zv[3], both, wgt, plus);
-            wd = recon(zw[1], zw[2], zw[3], both, wgt, plus);
-          } else if (d == 3) {  // donor plane k+1
-            ud = recon(zu[2], zu[3], zu[4], both, wgt, plus);
-            vd = recon(zv[2], zv[3], zv[4], both, wgt, plus);
-            wd = recon(zw[2], zw[3], zw[4], both, wgt, plus);
-          } else if (d == 1) {  // donor plane k-1
-            ud = recon(zu[0], zu[1], zu[2], both, wgt, plus);
-            vd = recon(zv[0], zv[1], zv[2], both, wgt, plus);
-            wd = recon(zw[0], zw[1], zw[2], both, wgt, plus);
-          } else {  // upper donor of the inflow edge: plane k
-            ud = recon(zu[1], zu[2], zu[3], both, wgt, plus);
-            vd = recon(zv[1], zv[2], zv[3], both, wgt, plus);
-            wd = recon(zw[1], zw[2], zw[3], both, wgt, plus);
-          }
-          flow(phi, ud, vd, wd, sgn);
-        };
-        // z edges: the dual face between node planes k and k+1 is that of the
-        // 4 cells of plane k, the one between k-1 and k that of plane k-1
-        if (k + 1 <= m.nz) zedge(2, za_m, za_v, R(-1));
-        if (k >= 1) zedge(1, zs_m, zs_v, R(1));
-        R un = R(0), vn = R(0), wn = R(0), dk = R(0);
-        if (!(mn > R(0))) {
-          atomicOr(&ctl->status, SALE_FLAG_NUMERIC);
-        } else {
-          const R imn = R(1) / mn;
-          un = P0 * imn;
-          vn = P1 * imn;
-          wn = P2 * imn;
-          if (gi == 0 || gi == m.nx) un = R(0);
-          if (gj == 0 || gj == m.ny) vn = R(0);
-          if (k == 0 || k == m.nz) wn = R(0);
-          dk = (K - R(0.5) * mn * (un * un + vn * vn + wn * wn)) * imn;
-        }
-        const int64_t q = nix + k * npl;
-        nxt.u[q] = un;
-        nxt.v[q] = vn;
-        nxt.w[q] = wn;
-        t.dk[q] = dk;
-      }
+    // Every dual edge is evaluated once: an in-plane edge by its lower node
+    // (the out-edge; the upper node takes it as its in-edge from LDS), a z edge
+    // at its lower node plane (carried to the next plane as that plane's lower
+    // edge). An edge's contribution is (phi u_d, phi v_d, phi w_d,
+    // phi |u_d|^2 / 2) with the donor's limited linear values u_d; the out-node
+    // subtracts it, the in-node adds it.
+    // donor value of one component: limited linear profile of the donor
+    // (values qm, q0, qp at the donor and its two neighbours along the edge)
+    auto recon = [&](R qm, R q0, R qp, bool both, R wgt, bool plus) {
+      return both ? donor_value(q0, vanleer(q0 - qm, qp - q0), wgt, plus) : q0;
+    };
+    auto contrib = [&](R phi, R ud, R vd, R wd, R *e) {
+      e[0] = phi * ud;
+      e[1] = phi * vd;
+      e[2] = phi * wd;
+      e[3] = phi * R(0.5) * (ud * ud + vd * vd + wd * wd);
+    };
+    // in-plane edge along x (ax 0) or y (ax 1) from the node at global index
+    // glo (this column) to glo + 1
+    auto inplane = [&](int ax, int nlim, int glo, R phi, R dv, R *e) {
+      const bool lower = phi > R(0);
+      const int dg = lower ? glo : glo + 1;
+      const bool both = dg >= 1 && dg + 1 <= nlim;
+      const R wgt = donor_weight(dv, ihA[ax]);
+      const bool plus = lower && dv != R(0);
+      const int dx = ax == 0, dy = ax == 1;
+      const int x0 = ci + (ax == 0 ? dg - gi : 0), y0 = cj + (ax == 1 ? dg - gj : 0);
+      const R ud = recon(LU[0][y0 - dy][x0 - dx], LU[0][y0][x0], LU[0][y0 + dy][x0 + dx], both, wgt, plus);
+      const R vd = recon(LU[1][y0 - dy][x0 - dx], LU[1][y0][x0], LU[1][y0 + dy][x0 + dx], both, wgt, plus);
+      const R wd = recon(LU[2][y0 - dy][x0 - dx], LU[2][y0][x0], LU[2][y0 + dy][x0 + dx], both, wgt, plus);
+      contrib(phi, ud, vd, wd, e);
+    };
+    // the out-edges along x of columns 1 .. NTX+1 and along y of rows 1 ..
+    // NTY+1 of the owned range (the first halo column / row gives the owned
+    // nodes' in-edges)
+    const bool inx = ci >= 2 && ci < 2 + NTX, iny = cj >= 2 && cj < 2 + NTY;
+    const bool xcomp = ncol && ci >= 1 && ci < 2 + NTX && iny && gi + 1 <= m.nx && k >= Z0;
+    const bool ycomp = ncol && cj >= 1 && cj < 2 + NTY && inx && gj + 1 <= m.ny && k >= Z0;
+    R ex[4] = {R(0), R(0), R(0), R(0)}, ey[4] = {R(0), R(0), R(0), R(0)}, ez[4] = {R(0), R(0), R(0), R(0)};
+    if (xcomp) {
+      // cells (i, j-1..j) of planes k-1 and k
+      const R phi = R(0.125) * ((C[MX][cj - 1][ci] + C[MX][cj - 1][ci + 1]) + (C[MX][cj][ci] + C[MX][cj][ci + 1]));
+      const R dv = R(0.125) * ((C[VX][cj - 1][ci] + C[VX][cj - 1][ci + 1]) + (C[VX][cj][ci] + C[VX][cj][ci + 1]));
+      inplane(0, m.nx, gi, phi, dv, ex);
     }
-    zs_m = za_m;
-    zs_v = za_v;
+    if (ycomp) {
+      // cells (i-1..i, j)
+      const R phi = R(0.125) * ((C[MY][cj][ci - 1] + C[MY][cj + 1][ci - 1]) + (C[MY][cj][ci] + C[MY][cj + 1][ci]));
+      const R dv = R(0.125) * ((C[VY][cj][ci - 1] + C[VY][cj + 1][ci - 1]) + (C[VY][cj][ci] + C[VY][cj + 1][ci]));
+      inplane(1, m.ny, gj, phi, dv, ey);
+    }
+    // the z edge from node plane k to k+1 (its dual face is that of the 4
+    // cells of plane k); the column's u' at node planes k-2..k+2 is window
+    // slots 0..4
+    if (own && k + 1 <= m.nz) {
+      const bool lower = za_m > R(0);
+      const int dg = lower ? k : k + 1;  // donor's node plane
+      const bool both = dg >= 1 && dg + 1 <= m.nz;
+      const R wgt = donor_weight(za_v, ihA[2]);
+      const bool plus = lower && za_v != R(0);
+      R ud, vd, wd;
+      if (lower) {  // donor plane k: slots 1..3
+        ud = recon(zu[1], zu[2], zu[3], both, wgt, plus);
+        vd = recon(zv[1], zv[2], zv[3], both, wgt, plus);
+        wd = recon(zw[1], zw[2], zw[3], both, wgt, plus);
+      } else {  // donor plane k+1: slots 2..4
+        ud = recon(zu[2], zu[3], zu[4], both, wgt, plus);
+        vd = recon(zv[2], zv[3], zv[4], both, wgt, plus);
+        wd = recon(zw[2], zw[3], zw[4], both, wgt, plus);
+      }
+      contrib(za_m, ud, vd, wd, ez);
+    }
+    const bool fin = own && k >= Z0;
+    const R mp = fin ? R(0.125) * (c4(C, MO)) : R(0), mn = fin ? R(0.125) * (c4(C, MN)) : R(0);
+    __syncthreads();  // the cell sums are read: their planes take the out-edges
+    C[0][cj][ci] = ex[0];
+    C[1][cj][ci] = ex[1];
+    C[2][cj][ci] = ex[2];
+    C[3][cj][ci] = ex[3];
+    C[4][cj][ci] = ey[0];
+    C[5][cj][ci] = ey[1];
+    C[6][cj][ci] = ey[2];
+    C[7][cj][ci] = ey[3];
+    __syncthreads();
+    if (fin) {
+      const R u1 = zu[2], v1 = zv[2], w1 = zw[2];
+      R P0 = mp * u1, P1 = mp * v1, P2 = mp * w1;
+      R K = R(0.5) * mp * (u1 * u1 + v1 * v1 + w1 * w1);
+      auto add = [&](R a0, R a1, R a2, R a3, R sgn) {
+        P0 += sgn * a0;
+        P1 += sgn * a1;
+        P2 += sgn * a2;
+        K += sgn * a3;
+      };
+      if (gi + 1 <= m.nx) add(ex[0], ex[1], ex[2], ex[3], R(-1));  // x out
+      if (gi >= 1) add(C[0][cj][ci - 1], C[1][cj][ci - 1], C[2][cj][ci - 1], C[3][cj][ci - 1], R(1));  // x in
+      if (gj + 1 <= m.ny) add(ey[0], ey[1], ey[2], ey[3], R(-1));  // y out
+      if (gj >= 1) add(C[4][cj - 1][ci], C[5][cj - 1][ci], C[6][cj - 1][ci], C[7][cj - 1][ci], R(1));  // y in
+      if (k + 1 <= m.nz) add(ez[0], ez[1], ez[2], ez[3], R(-1));  // z out
+      if (k >= 1) add(zl[0], zl[1], zl[2], zl[3], R(1));          // z in (carried)
+      R un = R(0), vn = R(0), wn = R(0), dk = R(0);
+      if (!(mn > R(0))) {
+        atomicOr(&ctl->status, SALE_FLAG_NUMERIC);
+      } else {
+        const R imn = R(1) / mn;
+        un = P0 * imn;
+        vn = P1 * imn;
+        wn = P2 * imn;
+        if (gi == 0 || gi == m.nx) un = R(0);
+        if (gj == 0 || gj == m.ny) vn = R(0);
+        if (k == 0 || k == m.nz) wn = R(0);
+        dk = (K - R(0.5) * mn * (un * un + vn * vn + wn * wn)) * imn;
+      }
+      const int64_t q = nix + k * npl;
+      nxt.u[q] = un;
+      nxt.v[q] = vn;
+      nxt.w[q] = wn;
+      t.dk[q] = dk;
+    }
+#pragma unroll
+    for (int q = 0; q < 4; q++) zl[q] = ez[q];
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < 4; q++) {
