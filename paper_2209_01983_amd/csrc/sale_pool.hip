@@ -25,9 +25,9 @@
 // (vmcnt 0 in every wave, then the block barrier) before it counts itself, and
 // a block that sees a phase counter move takes an agent-scope acquire (its
 // CU's L1 lines are dropped) before it reads. No tile writes the L2 back to
-// memory (the agent-scope release would, after every tile: that write-back,
-// not the work, was most of the time of a launch whose tiles met in memory);
-// the writes reach memory at the end of the kernel. Run-control
+// memory, as an agent-scope release after every tile would: where a run's
+// tiles met in memory, those write-backs took most of the launch's time. The
+// writes reach memory at the end of the kernel. Run-control
 // fields are accessed one way only during the launch: the counters, the
 // signal-speed maximum and the status flags by device-scope atomics, the step
 // fields (dt, t, step, done) by plain loads and stores on the run's XCD.
