@@ -122,3 +122,29 @@ def test_capped_waits_abort_the_advance_and_flag_their_runs(monkeypatch):
         assert st == ref[s][0], (s, st, ref[s][0])
         for k in FIELDS:
             assert np.array_equal(f[k], ref[s][1][k]), (s, k)
+
+
+@pytest.mark.parametrize("precision", [sale.SALE_FP64, sale.SALE_MIXED32])
+def test_batched_256_runs_persistent_bitwise_equals_lockstep(monkeypatch, precision):
+    """The benchmark's batch (256 runs, edges 16..64) advanced 40 steps by one
+    persistent launch gives every run bitwise the fields and clocks-free state
+    of the lockstep kernels: thousands of tile hand-offs per step through the
+    XCDs' L2s."""
+    import torch
+    from paper_2209_01983_amd import workloads
+    from paper_2209_01983_amd.inputs import BATCH_SEED, batch_mix
+
+    say("pool xcd: 256-run batch, persistent vs lockstep, precision", precision)
+    reqs = batch_mix(256, seed=BATCH_SEED)
+    monkeypatch.delenv("SALE_POOL_XCC_MASK", raising=False)
+    out = {}
+    for mode in ("1", "0"):
+        monkeypatch.setenv("SALE_POOL_PERSISTENT", mode)
+        r = workloads.run_batched(reqs, 40, precision)
+        pool = r["pool"]
+        out[mode] = [(pool.state(s), pool.fields(s, on_device=True)) for s in r["slots"]]
+        pool.close()
+    for (st_p, f_p), (st_l, f_l) in zip(out["1"], out["0"]):
+        assert st_p == st_l and st_p[1] == 40 and st_p[3] == 0, (st_p, st_l)
+        for k in FIELDS:
+            assert torch.equal(f_p[k], f_l[k]), k
