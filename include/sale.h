@@ -325,7 +325,8 @@ int sale_pool_admit(sale_pool *pool, const sale_config *cfg, const sale_problem 
  * the runs in the advance are copied from host memory), then enqueues the
  * advance and returns without waiting for it. The pool's first advance that
  * may take the persistent mode first runs a small kernel that lists the
- * device's XCD ids and waits for it. A failed capture or instantiation of the
+ * device's XCD ids and waits for it (SALE_EHIP if it finds none). A failed
+ * capture or instantiation of the
  * round graph returns SALE_EHIP after the first round was enqueued. */
 int sale_pool_advance(sale_pool *pool, int32_t max_steps_per_run);
 
